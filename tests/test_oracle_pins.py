@@ -1,0 +1,308 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself.
+
+Each test names the passage it checks.  A plausible mistake in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, a missed box) fails
+at least one of them:
+
+* golden closed forms of Eq. 1 (Section III) worked out by hand,
+* the force is minus the gradient of a pair energy obtained by integrating
+  Eq. 1 over the overlap, differentiated numerically,
+* degree-1 homogeneity under scaling by 2 (exact in binary floating point),
+* linearity in (kappa, gamma),
+* O(N^2) brute force for neighbour sets and forces (Section IV-A claims the 27
+  surrounding boxes hold every agent within the radius),
+* numpy's stable sort for the box order, exact rational arithmetic for box
+  membership,
+* antisymmetry (sum of forces ~ 0), axis permutations and reflections,
+  permutation of the input order,
+* the displacement rule of Section III (adherence, bound, m = 0 freeze).
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_00039_amd import workloads
+
+P = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "eq1_closed_forms.txt")
+
+
+def golden():
+    vals = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            case, q, v = line.split()
+            vals[(case, q)] = float(v)
+    return vals
+
+
+def pair(x2, d1=10.0, d2=10.0):
+    return (np.array([0.0, x2]), np.zeros(2), np.zeros(2), np.array([d1, d2]))
+
+
+# ---------------------------------------------------------------- golden ---
+
+def test_golden_two_body_cases():
+    g = golden()
+    F, D = oracle.step(*pair(9.0), P)
+    assert F[0, 0] == pytest.approx(g[("W1", "F1x")], rel=1e-15, abs=0)
+    assert F[1, 0] == pytest.approx(g[("W1", "F2x")], rel=1e-15, abs=0)
+    assert D[0, 0] == pytest.approx(g[("W1", "D1x")], rel=1e-15, abs=0)
+    assert np.all(F[:, 1:] == 0) and np.all(D[:, 1:] == 0)
+    F, _ = oracle.step(*pair(9.5), P)
+    assert F[0, 0] == pytest.approx(g[("W2", "F1x")], rel=1e-14)
+    assert F[0, 0] > 0  # adhesion pulls agent 1 toward agent 2 (+x)
+    for x2, key in ((10.0, "W3a"), (10.5, "W3b")):
+        F, D = oracle.step(*pair(x2), P)
+        assert np.all(F == g[(key, "F1x")]) and np.all(D == 0.0)
+    F, D = oracle.step(*pair(9.0), dict(P, dt=10.0))
+    assert D[0, 0] == g[("W4", "D1x")] and D[1, 0] == -g[("W4", "D1x")]
+    F, _ = oracle.step(*pair(9.0, 8.0, 12.0), P)
+    assert F[0, 0] == pytest.approx(g[("W5", "F1x")], rel=1e-15)
+    x = np.zeros(2)
+    F, D = oracle.step(x, x.copy(), x.copy(), np.array([10.0, 10.0]), P)
+    assert np.all(F == g[("W7", "F1x")]) and np.all(D == 0)
+
+
+def test_golden_lattice_block():
+    g = golden()
+    s1 = g[("W6", "s1")]
+    pop = workloads.lattice(side=3, spacing=9.0, jitter=0.0, dmin=10.0, dmax=10.0)
+    F, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    pos = np.stack([pop.x, pop.y, pop.z], axis=1)
+    for i in range(pop.n):
+        idx = np.rint(pos[i] / 9.0).astype(int)          # 0, 1, 2 per axis
+        expect = np.where(idx == 0, -s1, np.where(idx == 2, s1, 0.0))
+        np.testing.assert_allclose(F[i], expect, rtol=1e-15, atol=0)
+        if np.all(idx == 1):
+            assert np.all(F[i] == 0.0)                     # exact cancellation
+
+
+# --------------------------------------------------------- energy pin -----
+
+def pair_energy(pos, d, kappa, gamma):
+    """Energy whose negative gradient is Eq. 1: integrating
+    s(delta) = kappa*delta - gamma*sqrt(rho*delta) over the overlap gives
+    U = kappa*delta^2/2 - (2/3)*gamma*sqrt(rho)*delta^(3/2) per touching pair
+    (delta grows as the centres approach, so dU/dl = -s)."""
+    n = pos.shape[0]
+    E = 0.0
+    for i in range(n):
+        for j in range(i + 1, n):
+            l = float(np.linalg.norm(pos[i] - pos[j]))
+            ri, rj = d[i] / 2, d[j] / 2
+            delta = ri + rj - l
+            if delta > 0:
+                rho = ri * rj / (ri + rj)
+                E += kappa * delta ** 2 / 2 - (2.0 / 3.0) * gamma * np.sqrt(rho) * delta ** 1.5
+    return E
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_force_is_minus_energy_gradient(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 24
+    pos = rng.uniform(0, 22.0, size=(n, 3))
+    d = rng.uniform(8.0, 12.0, size=n)
+    kappa, gamma = 1.7, 0.8
+    F, _ = oracle.step(pos[:, 0], pos[:, 1], pos[:, 2], d, dict(P, kappa=kappa, gamma=gamma))
+    h = 1e-6
+    G = np.zeros_like(pos)
+    for i in range(n):
+        for k in range(3):
+            pp = pos.copy(); pp[i, k] += h
+            pm = pos.copy(); pm[i, k] -= h
+            G[i, k] = -(pair_energy(pp, d, kappa, gamma) - pair_energy(pm, d, kappa, gamma)) / (2 * h)
+    assert np.abs(F).max() > 0.5
+    np.testing.assert_allclose(F, G, rtol=0, atol=2e-6)
+
+
+# --------------------------------------------------- algebraic invariants ---
+
+def test_homogeneity_degree_one_exact():
+    pop = workloads.uniform(600, mean_neighbors=12.0, seed=3)
+    F1, D1 = oracle.step(pop.x, pop.y, pop.z, pop.d, dict(P, max_disp=1e9))
+    F2, D2 = oracle.step(2 * pop.x, 2 * pop.y, 2 * pop.z, 2 * pop.d, dict(P, max_disp=1e9))
+    assert np.array_equal(F2, 2 * F1)
+    assert np.array_equal(D2, 2 * D1)
+
+
+def test_linear_in_kappa_gamma():
+    pop = workloads.uniform(500, mean_neighbors=12.0, seed=4)
+    a = pop.x, pop.y, pop.z, pop.d
+    Fk, _ = oracle.step(*a, dict(P, kappa=1.0, gamma=0.0))
+    Fg, _ = oracle.step(*a, dict(P, kappa=0.0, gamma=1.0))
+    F, _ = oracle.step(*a, dict(P, kappa=2.5, gamma=0.75))
+    np.testing.assert_allclose(F, 2.5 * Fk + 0.75 * Fg, rtol=0, atol=1e-13)
+    # the kappa term alone pushes touching pairs apart: for a pair, F1 . (p1-p2) > 0
+    F, _ = oracle.step(*pair(9.3), dict(P, kappa=1.0, gamma=0.0))
+    assert F[0, 0] < 0 and F[0, 0] == pytest.approx(-0.7, rel=1e-14)  # delta = 0.7, e = -x
+    F, _ = oracle.step(*pair(9.3), dict(P, kappa=0.0, gamma=1.0))
+    assert F[0, 0] == pytest.approx(np.sqrt(2.5 * 0.7), rel=1e-14)   # pulled toward agent 2
+
+
+def test_antisymmetry_sum_is_rounding_small():
+    pop = workloads.uniform(3000, mean_neighbors=20.0, seed=5)
+    F, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    S, A, C = oracle.tolerance_scales(pop.x, pop.y, pop.z, pop.d, 2.0, 1.0, 2.0 ** -53)
+    total = np.abs(F.sum(axis=0))
+    assert C.sum() > 1000
+    assert np.all(total <= 64 * 2.0 ** -53 * S.sum())
+    # the scale S bounds the force (triangle inequality)
+    assert np.all(np.linalg.norm(F, axis=1) <= S * (1 + 1e-12))
+
+
+def test_axis_permutation_and_reflection():
+    pop = workloads.uniform(800, mean_neighbors=12.0, seed=6)
+    F, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    Fp, _ = oracle.step(pop.z, pop.x, pop.y, pop.d, P)     # axes rotated
+    np.testing.assert_allclose(Fp, F[:, [2, 0, 1]], rtol=0, atol=1e-13)
+    Fr, _ = oracle.step(-pop.x, pop.y, pop.z, pop.d, P)    # mirror in x
+    np.testing.assert_allclose(Fr, F * np.array([-1, 1, 1]), rtol=0, atol=1e-13)
+
+
+def test_input_permutation_equivariance():
+    pop = workloads.uniform(700, mean_neighbors=15.0, seed=7)
+    rng = np.random.default_rng(8)
+    q = rng.permutation(pop.n)
+    F, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    Fq, _ = oracle.step(pop.x[q], pop.y[q], pop.z[q], pop.d[q], P)
+    np.testing.assert_allclose(Fq, F[q], rtol=0, atol=1e-13)
+    c, o, l = oracle.neighbors(pop.x, pop.y, pop.z, pop.d)
+    cq, oq, lq = oracle.neighbors(pop.x[q], pop.y[q], pop.z[q], pop.d[q])
+    for k in range(pop.n):
+        assert set(q[lq[oq[k]:oq[k + 1]]]) == set(l[o[q[k]]:o[q[k] + 1]])
+
+
+# ------------------------------------------------------------ brute force ---
+
+def _cases():
+    yield "uniform", workloads.uniform(1500, mean_neighbors=12.0, seed=9)
+    yield "dense", workloads.uniform(1200, mean_neighbors=40.0, seed=10)
+    yield "lattice", workloads.lattice(side=10, seed=11)
+    yield "cluster", workloads.clusters(1500, n_clusters=3, side=200.0, seed=12)
+    r = np.random.default_rng(13)
+    t = r.uniform(0, 300, 400)
+    yield "collinear", workloads.Population(t, np.zeros(400), np.zeros(400), r.uniform(8, 12, 400))
+    yield "one_box", workloads.Population(*(r.uniform(0, 5, 300) for _ in range(3)), r.uniform(8, 12, 300))
+
+
+@pytest.mark.parametrize("name,pop", list(_cases()), ids=[c[0] for c in _cases()])
+def test_neighbor_sets_match_brute_force(name, pop):
+    _, e, _, _ = oracle.geometry(pop.x, pop.y, pop.z, pop.d)
+    c, o, l = oracle.neighbors(pop.x, pop.y, pop.z, pop.d)
+    cb, ob, lb = oracle.brute_neighbors(pop.x, pop.y, pop.z, e)
+    assert np.array_equal(c, cb)
+    box, _, _ = oracle.grid(pop.x, pop.y, pop.z, pop.d)
+    for i in range(pop.n):
+        mine = l[o[i]:o[i + 1]]
+        assert np.array_equal(np.sort(mine), lb[ob[i]:ob[i + 1]])
+        # canonical order: ascending box, then ascending index inside a box
+        key = box[mine].astype(np.int64) * pop.n + mine
+        assert np.all(np.diff(key) > 0)
+
+
+@pytest.mark.parametrize("name,pop", list(_cases()), ids=[c[0] for c in _cases()])
+def test_forces_match_brute_force(name, pop):
+    F, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    Fb = oracle.brute_forces(pop.x, pop.y, pop.z, pop.d, 2.0, 1.0)
+    S, _, _ = oracle.tolerance_scales(pop.x, pop.y, pop.z, pop.d, 2.0, 1.0, 2.0 ** -53)
+    err = np.linalg.norm(F - Fb, axis=1)
+    assert np.all(err <= 1e-14 * S + 1e-300)
+    nocontact = S == 0
+    assert np.all(F[nocontact] == 0) and np.all(Fb[nocontact] == 0)
+
+
+# ------------------------------------------------------------------ grid ---
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_grid_is_stable_counting_sort(seed):
+    pop = workloads.uniform(5000, mean_neighbors=6.0, seed=seed)
+    box, start, perm = oracle.grid(pop.x, pop.y, pop.z, pop.d)
+    n = pop.n
+    assert np.array_equal(perm, np.lexsort((np.arange(n), box)))
+    counts = np.bincount(box, minlength=start.size - 1)
+    assert np.array_equal(np.diff(start), counts)
+    assert start[0] == 0 and start[-1] == n
+
+
+def test_box_membership_exact():
+    pop = workloads.uniform(400, mean_neighbors=8.0, seed=14)
+    o, e, dims, nb = oracle.geometry(pop.x, pop.y, pop.z, pop.d)
+    assert e == pop.d.max()
+    assert nb == int(np.prod(dims))
+    box, _, _ = oracle.grid(pop.x, pop.y, pop.z, pop.d)
+    E = Fraction(e)
+    pos = (pop.x, pop.y, pop.z)
+    for k in range(3):
+        span = Fraction(float(pos[k].max())) - Fraction(float(o[k]))
+        assert (dims[k] - 1) * E <= span < dims[k] * E      # fewest boxes covering the span
+    for i in range(pop.n):
+        b = int(box[i])
+        ix, iy, iz = b % dims[0], (b // dims[0]) % dims[1], b // (dims[0] * dims[1])
+        for k, c in enumerate((ix, iy, iz)):
+            rel = Fraction(float(pos[k][i])) - Fraction(float(o[k]))
+            assert c * E <= rel < (c + 1) * E
+
+
+# ------------------------------------------------- displacement rule ------
+
+def test_displacement_rule():
+    pop = workloads.uniform(800, mean_neighbors=12.0, seed=15)
+    a = pop.x, pop.y, pop.z, pop.d
+    F, D = oracle.step(*a, dict(P, dt=0.5, max_disp=0.2))
+    fn = np.linalg.norm(F, axis=1)
+    dn = np.linalg.norm(D, axis=1)
+    assert np.all(dn <= 0.2 * (1 + 4e-16))
+    clamped = 0.5 * fn > 0.2
+    assert clamped.sum() > 10 and (~clamped & (fn > 0)).sum() > 10
+    np.testing.assert_allclose(dn[clamped], 0.2, rtol=1e-15)
+    np.testing.assert_allclose(D[~clamped], 0.5 * F[~clamped], rtol=0, atol=0)
+    # direction preserved
+    cos = np.sum(D[clamped] * F[clamped], axis=1) / (dn[clamped] * fn[clamped])
+    np.testing.assert_allclose(cos, 1.0, rtol=1e-14)
+    # m = 0 freezes every agent (the paper's density benchmark)
+    _, D0 = oracle.step(*a, dict(P, max_disp=0.0))
+    assert np.all(D0 == 0)
+    # adherence: agents whose force does not exceed a stay put
+    thr = float(np.median(fn[fn > 0]))
+    _, Da = oracle.step(*a, dict(P, adherence=thr))
+    held = fn <= thr
+    assert np.all(Da[held] == 0)
+    np.testing.assert_array_equal(Da[~held], (0.01 * F)[~held])
+
+
+# ------------------------------------------------------------- edge cases ---
+
+def test_edge_cases():
+    e = np.zeros(0)
+    F, D = oracle.step(e, e, e, e, P)
+    assert F.shape == (0, 3)
+    one = np.array([3.0])
+    F, D = oracle.step(one, one, one, np.array([10.0]), P)
+    assert np.all(F == 0)
+    o, edge, dims, nb = oracle.geometry(one, one, one, np.array([10.0]))
+    assert list(dims) == [1, 1, 1] and nb == 1
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.step(np.array([0.0, np.nan]), np.zeros(2), np.zeros(2), np.ones(2) * 10, P)
+    assert ei.value.code == oracle.EINPUT
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.step(np.array([0.0, 1.0]), np.zeros(2), np.zeros(2), np.array([10.0, -1.0]), P)
+    assert ei.value.code == oracle.EINPUT
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.grid(np.array([0.0, 1.0]), np.zeros(2), np.zeros(2), np.array([10.0, 10.0]), edge=5.0)
+    assert ei.value.code == oracle.EINVAL
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.step(*pair(9.0), dict(P, dt=-1.0))
+    assert ei.value.code == oracle.EINVAL
+    # a larger edge than the largest diameter gives the same forces
+    pop = workloads.uniform(500, mean_neighbors=12.0, seed=16)
+    F1, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
+    F2, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P, edge=30.0)
+    np.testing.assert_allclose(F1, F2, rtol=0, atol=1e-13)
