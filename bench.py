@@ -1,0 +1,347 @@
+"""Benchmark of the mechanical-interaction step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
+                    [--neighbors 12] [--no-cpu] [--no-extras]
+
+A step is one pass of the whole hot path over the population: uniform-grid
+build (bounds, binning, counts, scan, stable scatter), 27-box gather with the
+Eq. 1 force and the displacement rule, and the position update.  The headline
+workload is 2,097,152 agents uniform in a cube sized for ~12 neighbours within
+the interaction radius 12, diameters U[8, 12], FP32.  Inputs are resident in
+device memory before timing starts.  The timed region replays a HIP graph of
+one step K times.
+
+One JSON line is printed with, besides the headline value:
+  roofline      the force kernel's algorithmic flops per launch (9 per
+                27-box candidate + 25 per contact, the measured candidate and
+                contact counts of the workload) over its mean duration from HIP
+                events around every force launch of an eager K-step pass,
+                against the FP32 vector peak; traffic from rocprofv3 counters
+                is filled from the committed profile summary when present.
+  cpu_baseline  the FP64 oracle (single thread) on the same population.
+  variants      other densities / FP64, fwd+bwd and the batched workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "agent-steps/s mech step @2M agents: plain vs batched vs fwd+bwd; % HBM peak"
+HBM_PEAK = 8.0e12            # B/s
+FP32_PEAK = 157.3e12         # flop/s, published FP32 vector peak
+FP64_PEAK = 78.6e12
+PARAMS = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bytes_alg(n, n_boxes, S):
+    """Algorithmic bytes of a whole step: 22S + 16 per agent and 20 per box."""
+    return (22 * S + 16) * n + 20 * n_boxes
+
+
+def force_bytes(n, n_boxes, S):
+    """Force kernel: payload 4S + perm 4 read, 3S written per agent; start 4 per box."""
+    return (7 * S + 4) * n + 4 * n_boxes
+
+
+def workload_stats(ms, ws, n):
+    """Mean 27-box candidates C, contacts K, neighbours within the radius and
+    occupancy, from the exported grid and neighbour lists."""
+    import torch
+    g = ms.grid_get(ws)
+    info = g["info"][0]
+    nx, ny, nz = info["dims"]
+    start = g["start"].cpu().numpy().astype(np.int64)
+    cnt = np.diff(start).reshape(nz, ny, nx)
+    pad = np.pad(cnt, 1)
+    box27 = np.zeros_like(cnt)
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                box27 += pad[dz:dz + nz, dy:dy + ny, dx:dx + nx]
+    C = float(np.sum(cnt * (box27 - 1)) / n)
+    counts, offsets, lst = ms.neighbors(ws)
+    return dict(candidates=C, neighbors=float(counts.double().mean().item()),
+                n_boxes=int(info["n_boxes"]), occupancy=n / max(int(info["n_boxes"]), 1),
+                dims=list(info["dims"]), edge=info["edge"], lists=(counts, offsets, lst))
+
+
+def contacts_per_agent(x, y, z, d, counts, lst):
+    import torch
+    i = torch.repeat_interleave(torch.arange(counts.numel(), device=counts.device), counts.long())
+    j = lst.long()
+    X, Y, Z, D = (t.double() for t in (x, y, z, d))
+    l = torch.sqrt((X[i] - X[j]) ** 2 + (Y[i] - Y[j]) ** 2 + (Z[i] - Z[j]) ** 2)
+    K = ((D[i] + D[j]) / 2 - l > 0).sum().item()
+    return K / counts.numel()
+
+
+def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, backward=False):
+    """Returns (seconds for `steps` steps, mean force-kernel ms or None)."""
+    n = arrs[0].size
+    ws = ms.Workspace(n, dtype=dtype)
+    in_t = torch.float32 if dtype == "f32" else torch.float64
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in arrs]
+    x0 = [a.clone() for a in t[:3]]
+    out = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+    gout = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(4))
+    gkg = torch.empty(2, dtype=torch.float64, device="cuda")
+    gin = tuple(torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+
+    def one(ev=None):
+        ms.grid_build(ws, *t)
+        if ev is not None:
+            ev[0].record()
+        ms.mech_step(ws, PARAMS, out=out)
+        if ev is not None:
+            ev[1].record()
+        if backward:
+            ms.mech_step_backward(ws, PARAMS, *gin, out=gout, g_params=gkg)
+        ms.integrate(*t[:3], *out)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    ms.device_status(ws)
+    force_ms = None
+    if events:
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for k in range(steps):
+            one(evs[k])
+        b.record()
+        torch.cuda.synchronize()
+        force_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        total = a.elapsed_time(b) / 1e3
+    elif graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            one()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            one()
+        for _ in range(max(warmup, 1)):
+            gr.replay()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            gr.replay()
+        b.record()
+        torch.cuda.synchronize()
+        total = a.elapsed_time(b) / 1e3
+    else:
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            one()
+        b.record()
+        torch.cuda.synchronize()
+        total = a.elapsed_time(b) / 1e3
+    ms.device_status(ws)
+    for a_, b_ in zip(t[:3], x0):
+        a_.copy_(b_)
+    return total, force_ms, ws, t
+
+
+def time_batched(ms, torch, steps, warmup, seed=0):
+    from paper_2105_00039_amd import workloads
+    b = workloads.batched(seed=seed)
+    n = b.n
+    ws = ms.Workspace(n, max_sims=b.n_sims, dtype="f32_pos64")
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in b.arrays(np.float64)]
+    spec = ms.BatchSpec(b.offsets)
+    P = ms.params_tensor([dict(PARAMS, kappa=float(k), gamma=float(g)) for k, g in zip(b.kappa, b.gamma)],
+                         "cuda")
+    out = tuple(torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+
+    def one():
+        ms.grid_build_batched(ws, *t, spec)
+        ms.mech_step_batched(ws, P, out=out)
+        ms.integrate(*t[:3], *out)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    ms.device_status(ws)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        one()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        one()
+    gr.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        gr.replay()
+    e.record()
+    torch.cuda.synchronize()
+    ms.device_status(ws)
+    sec = a.elapsed_time(e) / 1e3
+    return dict(value=n * steps / sec, unit="agent-steps/s", n_sims=b.n_sims, n_agents=n, steps=steps,
+                ms_per_step=sec / steps * 1e3, dtype="f32 force, f64 positions",
+                workload="batched256: sizes 10^U(3,5), 4-30 neighbours, kappa U[1,4], gamma U[0.5,2]")
+
+
+def cpu_baseline(arrs, budget_s=12.0, max_steps=3):
+    import oracle
+    a64 = [np.asarray(a, dtype=np.float64) for a in arrs]
+    n = a64[0].size
+    done = 0
+    t0 = time.perf_counter()
+    while done < max_steps:
+        oracle.step(*a64, PARAMS)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    sec = time.perf_counter() - t0
+    return dict(value=n * done / sec, unit="agent-steps/s", cores=1, kind="oracle",
+                sample=f"{done} full step(s) (grid + force + displacement) of the same {n}-agent "
+                       f"population, FP64, single thread, {sec:.1f} s")
+
+
+def traffic_from_profiles(kernel="k_force", workload="uniform2M_n12_f32"):
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            return json.load(f).get("hbm_bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--neighbors", type=float, default=12.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the eager K-step pass (for rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the step has no multi-GPU path in this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2105_00039_amd as ms
+    from paper_2105_00039_amd import workloads
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    N = workloads.FULL_N
+    pop = workloads.uniform(N, mean_neighbors=args.neighbors, seed=args.seed)
+    np_in = np.float32 if args.dtype == "f32" else np.float64
+    arrs = [a.astype(np_in) for a in pop.arrays()]
+    S = 4 if args.dtype == "f32" else 8
+    name = f"uniform2M_n{args.neighbors:g}"
+    log(f"workload {name} {args.dtype}: {N} agents, cube side {pop.meta['side']:.1f}")
+
+    if args.profile_only:
+        sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
+        log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
+        return
+
+    # headline: graph-replayed steps
+    sec, _, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True)
+    value = N * args.steps / sec
+    log(f"graph {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, {value:.3e} agent-steps/s")
+    # roofline of the force kernel: eager pass with events around each launch
+    sec_e, force_ms, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
+    log(f"eager {args.steps} steps: {sec_e * 1e3 / args.steps:.3f} ms/step, force kernel {force_ms * 1e3:.1f} us")
+    ms.grid_build(ws, *t)
+    st = workload_stats(ms, ws, N)
+    counts, offsets, lst = st.pop("lists")
+    K = contacts_per_agent(*t, counts, lst)
+    del counts, offsets, lst
+    flops_agent = 9 * st["candidates"] + 25 * K
+    flops = flops_agent * N
+    peak = FP32_PEAK if args.dtype == "f32" else FP64_PEAK
+    achieved = flops / (force_ms * 1e-3)
+    fb = force_bytes(N, st["n_boxes"], S)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=traffic_from_profiles(workload=f"{name}_{args.dtype}"),
+                    kernel="k_force", flops_per_agent=flops_agent, force_us=force_ms * 1e3,
+                    force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9)
+    balg = bytes_alg(N, st["n_boxes"], S)
+    hbm = dict(step_alg_bytes=balg, step_alg_GBps=balg * args.steps / sec / 1e9,
+               frac_of_peak=balg * args.steps / sec / HBM_PEAK)
+    log(f"C={st['candidates']:.1f} K={K:.2f} nbrs={st['neighbors']:.2f} boxes={st['n_boxes']} "
+        f"force {achieved / 1e12:.1f} TF/s; step {hbm['step_alg_GBps']:.0f} GB/s alg")
+
+    extras = {}
+    if not args.no_extras:
+        other = "f64" if args.dtype == "f32" else "f32"
+        oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
+        s2, _, _, _ = time_plain(ms, torch, oarrs, other, args.steps, args.warmup, graph=True)
+        extras[f"plain_{other}_n{args.neighbors:g}"] = N * args.steps / s2
+        for nb in (4.0, 30.0):
+            p2 = workloads.uniform(N, mean_neighbors=nb, seed=args.seed)
+            a2 = [a.astype(np_in) for a in p2.arrays()]
+            s3, _, _, _ = time_plain(ms, torch, a2, args.dtype, args.steps, args.warmup, graph=True)
+            extras[f"plain_{args.dtype}_n{nb:g}"] = N * args.steps / s3
+        s4, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
+                                 backward=True)
+        fwd_bwd = dict(value=N * args.steps / s4, unit="agent-steps/s", ms_per_step=s4 / args.steps * 1e3,
+                       what="grid build + forward + backward + integrate, same workload")
+        batched = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup)
+        log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; batched {batched['value']:.3e}")
+    else:
+        fwd_bwd = batched = None
+
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline ...")
+        cpu = cpu_baseline(arrs)
+        log(f"oracle {cpu['value']:.3e} agent-steps/s")
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": name, "n_agents": N, "mean_neighbors_target": args.neighbors,
+                   "measured_neighbors": st["neighbors"], "contacts_per_agent": K,
+                   "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
+                   "diameters": "U[8,12]", "params": PARAMS, "graph": True},
+        "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
+        "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

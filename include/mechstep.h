@@ -1,0 +1,213 @@
+/*
+ * mechstep.h -- C ABI of the mechanical-interaction step for spherical agents
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation follows "GPU Acceleration of 3D Agent-Based Biological
+ * Simulations" (arXiv 2105.00039):
+ *   - Section III, Eq. 1: the force between two touching spheres,
+ *       delta = r1 + r2 - |p1 - p2|,   rho = r1 r2 / (r1 + r2),
+ *       F     = (kappa delta - gamma sqrt(rho delta)) (p1 - p2)/|p1 - p2|,
+ *     summed over every agent in contact; then the displacement: no motion
+ *     unless the force breaks the adherence, otherwise the force integrated
+ *     over the timestep, bounded in length.
+ *   - Section IV-A: neighbours are found through a uniform grid of voxels
+ *     ("boxes") rebuilt every step; an agent's candidates are the agents of the
+ *     27 boxes around its own.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller unless
+ *   the comment says "host".  Arrays are contiguous, one value per agent
+ *   (structure of arrays).  Element types follow the workspace dtype:
+ *     MS_F32       positions/diameters float,  displacements float
+ *     MS_F64       positions/diameters double, displacements double
+ *     MS_F32_POS64 positions/diameters double (master copy), the step itself
+ *                  runs in FP32 on the positions rounded to nearest float,
+ *                  displacements float.
+ *   Inputs and outputs must not alias.  Outputs are overwritten, never
+ *   accumulated.  Displacements and gradients are in the caller's agent order.
+ * Workspace.  All scratch lives in one caller-allocated device buffer sized by
+ *   ms_workspace_bytes() and described by an ms_workspace struct (host memory,
+ *   owned by the caller) set up once with ms_workspace_init().  Step calls
+ *   never allocate, never synchronise the host and use only kernel launches,
+ *   so a sequence of them can be captured into a HIP graph.
+ *   ms_mech_step* read the state copied by the last ms_grid_build* on the same
+ *   workspace, so the caller may update positions in place after the build.
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the null
+ *   stream.  Every call is ordered on that stream.  Calls on different
+ *   workspaces are independent; calls that share a workspace must be ordered.
+ * Errors.  Problems the host can see (null or misaligned pointer, size out of
+ *   range, wrong dtype, non-finite or negative dt / max_disp / adherence, a
+ *   workspace that is too small) return a status at once and set
+ *   ms_last_error() (thread-local).  Problems only the device can see
+ *   (non-finite or negative input values, an edge below the largest diameter,
+ *   more boxes than the workspace holds) set an error word in the workspace;
+ *   later kernels of the same workspace then do nothing and the outputs are
+ *   unspecified.  ms_device_status() synchronises the stream and reports it.
+ *   n = 0 is valid and does nothing.
+ * Limits.  Agents and boxes are indexed with int32: n < 2^31 and the total
+ *   number of boxes < 2^31.
+ */
+#ifndef MECHSTEP_H
+#define MECHSTEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MS_OK = 0,
+    MS_EINVAL = 1,     /* bad argument, or (device) edge <= 0 / edge < max diameter */
+    MS_ECAPACITY = 2,  /* more agents, boxes or simulations than the workspace holds */
+    MS_EDEVICE = 3,    /* a HIP runtime call failed */
+    MS_EINPUT = 4      /* (device) non-finite position/diameter or negative diameter */
+} ms_status;
+
+typedef enum {
+    MS_F32 = 0,
+    MS_F64 = 1,
+    MS_F32_POS64 = 2
+} ms_dtype;
+
+/* Force and displacement parameters (Section III, Eq. 1 and the text after it).
+ *   kappa      repulsion coefficient
+ *   gamma      attraction (adhesion) coefficient
+ *   dt         timestep of the overdamped integration: v = dt * F  (>= 0)
+ *   max_disp   upper bound m on the displacement length (>= 0; 0 freezes)
+ *   adherence  the agent moves only if |F| > adherence (>= 0)               */
+typedef struct {
+    double kappa, gamma, dt, max_disp, adherence;
+} ms_params;
+
+/* Geometry of one simulation's grid (Section IV-A), as built on the device. */
+typedef struct {
+    double  origin[3];  /* per-axis minimum position */
+    double  edge;       /* box edge = interaction radius */
+    int32_t dims[3];    /* boxes per axis: floor((max - min)/edge) + 1 */
+    int32_t error;      /* device error bits of the build (0 = fine) */
+    int64_t n_boxes;    /* dims[0]*dims[1]*dims[2] */
+    int64_t box_base;   /* first global box index of this simulation */
+    int64_t n_agents;   /* agents of this simulation */
+} ms_grid_info;
+
+/* Host-side description of a workspace.  Filled by ms_workspace_init; the
+ * fields after `dtype` are updated by the grid builds.  Treat as read-only. */
+typedef struct {
+    void*   base;        /* device buffer, 256-byte aligned */
+    size_t  bytes;
+    int64_t max_agents;  /* capacity: agents over all simulations */
+    int64_t max_boxes;   /* capacity: boxes over all simulations */
+    int32_t max_sims;    /* capacity: simulations (1 for the plain step) */
+    int32_t dtype;       /* ms_dtype */
+    int64_t n_agents;    /* agents of the last grid build */
+    int32_t n_sims;      /* simulations of the last grid build */
+    int32_t built;       /* 1 after a plain build, 2 after a batched build */
+} ms_workspace;
+
+/* Bytes of device memory a workspace with these capacities needs. */
+size_t ms_workspace_bytes(int64_t max_agents, int64_t max_boxes, int32_t max_sims,
+                          ms_dtype dtype);
+
+/* Describe `base` (>= ms_workspace_bytes(...) bytes, 256-byte aligned device
+ * memory) as a workspace and clear its device state (kernel launch on
+ * `stream`).  Must be called once before the first build. */
+ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t max_agents,
+                            int64_t max_boxes, int32_t max_sims, ms_dtype dtype, void* stream);
+
+/* Uniform grid (Section IV-A), rebuilt from scratch:
+ *   bounds -> box index per agent -> per-box counts -> exclusive scan ->
+ *   stable scatter into box-sorted order (ascending box, then ascending input
+ *   index inside a box) with a sorted copy of x, y, z, d/2.
+ * x, y, z, d: [n] device arrays of the workspace dtype.
+ * edge: box edge; <= 0 selects the largest diameter.  An edge below the
+ *   largest diameter is a device error (a contact could leave the 27 boxes). */
+ms_status ms_grid_build(ms_workspace* ws, const void* x, const void* y, const void* z,
+                        const void* d, int64_t n, double edge, void* stream);
+
+/* One mechanical step on the last plain build: for every agent the Eq. 1
+ * force summed over its contacts among the 27 surrounding boxes, then the
+ * displacement (Section III).  p: host pointer to the parameters.
+ * dx, dy, dz: [n] outputs. */
+ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, void* dy,
+                       void* dz, void* stream);
+
+/* Reverse-mode derivative of ms_mech_step on the same build (derived from
+ * Eq. 1 and the displacement rule; the paper itself has no backward pass).
+ * gdx..gdz: [n] dL/dDisplacement.  Outputs:
+ *   gx, gy, gz [n]  sum_k (dDelta_k/dp_i)^T g_k   (no identity term)
+ *   gd [n]          sum_k (dDelta_k/dd_i)^T g_k
+ *   g_params        device double[2] = {dL/dkappa, dL/dgamma}
+ * Sums are taken in a fixed order, so repeated calls give identical bits.
+ * Kinks: delta = 0 is no contact, |v| = max_disp is unclamped, |F| =
+ * adherence is held (the inactive side). */
+ms_status ms_mech_step_backward(const ms_workspace* ws, const ms_params* p,
+                                const void* gdx, const void* gdy, const void* gdz,
+                                void* gx, void* gy, void* gz, void* gd, double* g_params,
+                                void* stream);
+
+/* Batched grid: B independent simulations concatenated; simulation b owns
+ * agents [sim_offsets[b], sim_offsets[b+1]).  Each gets its own grid
+ * (origin, edge, dims) and a disjoint range of global box indices, and all
+ * are sorted together in one counting sort.
+ * sim_offsets: device int64 [B+1], non-decreasing, sim_offsets[0] = 0,
+ *   sim_offsets[B] = n_total (the host must pass the same n_total).
+ * edges: device double [B], or NULL for "largest diameter of each
+ *   simulation". */
+ms_status ms_grid_build_batched(ms_workspace* ws, const void* x, const void* y, const void* z,
+                                const void* d, const int64_t* sim_offsets, int32_t n_sims,
+                                int64_t n_total, const double* edges, void* stream);
+
+/* ms_mech_step for every simulation of the last batched build in one launch.
+ * params: device ms_params [B] (per-simulation kappa, gamma, dt, ...). */
+ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, void* dx,
+                               void* dy, void* dz, void* stream);
+
+/* ms_mech_step_backward per simulation; g_params: device double [2B]. */
+ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
+                                        const void* gdx, const void* gdy, const void* gdz,
+                                        void* gx, void* gy, void* gz, void* gd,
+                                        double* g_params, void* stream);
+
+/* p <- p + Delta for n agents (all agents move at once from the displacements
+ * of one step).  dtype: MS_F32 (float p, float Delta), MS_F64 (double,
+ * double) or MS_F32_POS64 (double p, float Delta, summed in FP64). */
+ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
+                       const void* dz, int64_t n, ms_dtype dtype, void* stream);
+
+/* Copy out the last build (synchronises `stream`).  info: host array with
+ * one entry per simulation (n_sims of the build).  box_id [n] (global box of
+ * each agent, caller order), box_start [total boxes + 1] (first sorted slot
+ * of each box), perm [n] (perm[slot] = input index): device arrays, each may
+ * be NULL. */
+ms_status ms_grid_get(const ms_workspace* ws, ms_grid_info* info, int32_t* box_id,
+                      int32_t* box_start, int32_t* perm, void* stream);
+
+/* Neighbour sets of the last build: for every agent i the agents j != i of
+ * the 27 surrounding boxes with |p_i - p_j|^2 < edge^2, evaluated in FP64 as
+ * (dx*dx + dy*dy) + dz*dz without fused multiply-add, listed in ascending box
+ * then ascending input index (Sections III and IV-A).
+ * counts [n] int32 and offsets [n+1] int64 (exclusive prefix of counts) are
+ * always written; list (int32, `cap` entries) is written when non-NULL and
+ * cap >= offsets[n], else MS_ECAPACITY.  Synchronises `stream` (it reads the
+ * total back) and returns the total through *total when non-NULL. */
+ms_status ms_neighbors(const ms_workspace* ws, int32_t* counts, int64_t* offsets,
+                       int32_t* list, int64_t cap, int64_t* total, void* stream);
+
+/* Synchronise `stream` and translate the workspace's device error word:
+ * MS_OK, MS_EINPUT, MS_EINVAL or MS_ECAPACITY. */
+ms_status ms_device_status(const ms_workspace* ws, void* stream);
+
+/* Streaming copy of `bytes` bytes (multiple of 16) from src to dst: the
+ * bandwidth probe used as the empirical HBM roof. */
+ms_status ms_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ms_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MECHSTEP_H */

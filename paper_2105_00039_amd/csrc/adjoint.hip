@@ -1,0 +1,283 @@
+// Reverse-mode derivative of the mechanical step (Eq. 1 and the displacement
+// rule of Section III; the paper itself has no backward pass).
+//
+// Given g_i = dL/dDelta_i:
+//   k_bwd_fbar    recompute F_i with the forward gather and pull g_i back
+//                 through the displacement rule:
+//                   |F| <= a : Fbar = 0
+//                   |v| <= m : Fbar = dt g
+//                   else     : Fbar = dt (m/|v|) (g - vhat (vhat . g))
+//                 Fbar is stored in box-sorted order.
+//   k_bwd_gather  for every contact (i, j), with e = (p_i - p_j)/l,
+//                 w = Fbar_i - Fbar_j, q = e . w,
+//                   s_delta = kappa - gamma rho / (2 sqrt(rho delta)),
+//                   s_rho   = -gamma delta / (2 sqrt(rho delta)):
+//                   pbar_i += (s/l)(w - e q) - s_delta q e
+//                   rbar_i += q (s_delta + s_rho r_j^2/(r_i + r_j)^2)
+//                   kbar   += delta (e . Fbar_i)
+//                   gbar   += -sqrt(rho delta) (e . Fbar_i)
+//                 The same 27-box runs as the forward pass; no atomics: every
+//                 agent accumulates only its own terms.  kbar and gbar are
+//                 summed per block (fixed tree) into one partial per
+//                 (block, simulation) pair at index block + simulation.
+//   k_reduce_params  one block per simulation sums its partials in a fixed
+//                 order, so repeated runs give identical bits.
+#include "gather.hpp"
+#include "launch.hpp"
+
+namespace ms {
+namespace {
+
+template <int M, bool BATCHED>
+__global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay* __restrict__ pay,
+                                                     const int32_t* __restrict__ start,
+                                                     const int32_t* __restrict__ perm,
+                                                     const SimGeom* __restrict__ geom,
+                                                     const int64_t* __restrict__ off, int32_t B,
+                                                     int64_t n, ms_params p1,
+                                                     const ms_params* __restrict__ pB,
+                                                     const Header* __restrict__ hdr,
+                                                     const typename Mode<M>::Real* __restrict__ gdx,
+                                                     const typename Mode<M>::Real* __restrict__ gdy,
+                                                     const typename Mode<M>::Real* __restrict__ gdz,
+                                                     typename Mode<M>::Pay* __restrict__ fbar)
+{
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    if (hdr->error) return;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t k = k0 + threadIdx.x;
+    int s = 0;
+    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (k >= n) return;
+    const SimGeom g = geom[s];
+    const ms_params P = BATCHED ? pB[s] : p1;
+    const Pay pi = pay[k];
+    const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
+    Real fx, fy, fz;
+    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, fx, fy, fz);
+    const int32_t o = perm[k];
+    const Real gx = gdx[o], gy = gdy[o], gz = gdz[o];
+    const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
+    Pay fb;
+    fb.w = (Real)0;
+    const Real fn = fsqrt(fx * fx + fy * fy + fz * fz);
+    if (!(fn > a)) {
+        fb.x = fb.y = fb.z = (Real)0;
+    } else {
+        const Real vx = dt * fx, vy = dt * fy, vz = dt * fz;
+        const Real vn = fsqrt(vx * vx + vy * vy + vz * vz);
+        if (vn > m) {
+            const Real hx = vx / vn, hy = vy / vn, hz = vz / vn;
+            const Real hg = hx * gx + hy * gy + hz * gz;
+            const Real sc = dt * (m / vn);
+            fb.x = sc * (gx - hx * hg);
+            fb.y = sc * (gy - hy * hg);
+            fb.z = sc * (gz - hz * hg);
+        } else {
+            fb.x = dt * gx;
+            fb.y = dt * gy;
+            fb.z = dt * gz;
+        }
+    }
+    fbar[k] = fb;
+}
+
+// Deterministic block sum: butterfly inside each wave, waves in fixed order.
+__device__ __forceinline__ double block_sum_fixed(double v, double* s_w)
+{
+    v = wave_sum<double>(v);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+    __syncthreads();
+    return t;
+}
+
+template <int M, bool BATCHED>
+__global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::Pay* __restrict__ pay,
+                                                       const typename Mode<M>::Pay* __restrict__ fbar,
+                                                       const int32_t* __restrict__ start,
+                                                       const int32_t* __restrict__ perm,
+                                                       const SimGeom* __restrict__ geom,
+                                                       const int64_t* __restrict__ off, int32_t B,
+                                                       int64_t n, ms_params p1,
+                                                       const ms_params* __restrict__ pB,
+                                                       const Header* __restrict__ hdr,
+                                                       typename Mode<M>::Real* __restrict__ gx,
+                                                       typename Mode<M>::Real* __restrict__ gy,
+                                                       typename Mode<M>::Real* __restrict__ gz,
+                                                       typename Mode<M>::Real* __restrict__ gd,
+                                                       double* __restrict__ partials)
+{
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    __shared__ double s_w[kBlock / kWave];
+    __shared__ int s_rng[2];
+    if (hdr->error) return;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t k = k0 + threadIdx.x;
+    int s = 0;
+    if (BATCHED) {
+        s = block_sim(off, B, n, k0, k);
+        if (threadIdx.x == 0) {
+            const int64_t last = (k0 + kBlock < n ? k0 + kBlock : n) - 1;
+            s_rng[0] = find_sim(off, 0, B, k0);
+            s_rng[1] = find_sim(off, 0, B, last);
+        }
+        __syncthreads();
+    }
+    double kb = 0.0, gb = 0.0;
+    if (k < n) {
+        const SimGeom g = geom[s];
+        const ms_params P = BATCHED ? pB[s] : p1;
+        const Real kap = (Real)P.kappa, gam = (Real)P.gamma;
+        const Pay pi = pay[k];
+        const Pay fi = fbar[k];
+        const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
+        Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
+        for_each_run(g, c, start, [&](int j0, int j1) {
+            for (int j = j0; j < j1; ++j) {
+                const Pay q = pay[j];
+                const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+                const Real l2 = ux * ux + uy * uy + uz * uz;
+                const Real rs = pi.w + q.w;
+                if (l2 < rs * rs && l2 > (Real)0) {
+                    const Real l = fsqrt(l2);
+                    const Real delta = rs - l;
+                    if (delta > (Real)0) {
+                        const Pay fj = fbar[j];
+                        const Real il = (Real)1 / l;
+                        const Real ex = ux * il, ey = uy * il, ez = uz * il;
+                        const Real rho = pi.w * q.w / rs;
+                        const Real sq = fsqrt(rho * delta);
+                        const Real sv = kap * delta - gam * sq;
+                        const Real h = (Real)0.5 / sq;
+                        const Real s_d = kap - gam * rho * h;
+                        const Real s_r = -gam * delta * h;
+                        const Real wx = fi.x - fj.x, wy = fi.y - fj.y, wz = fi.z - fj.z;
+                        const Real qv = ex * wx + ey * wy + ez * wz;
+                        const Real sl = sv * il;
+                        px += sl * (wx - ex * qv) - s_d * qv * ex;
+                        py += sl * (wy - ey * qv) - s_d * qv * ey;
+                        pz += sl * (wz - ez * qv) - s_d * qv * ez;
+                        rb += qv * (s_d + s_r * (q.w * q.w) / (rs * rs));
+                        const Real eF = ex * fi.x + ey * fi.y + ez * fi.z;
+                        kbl += delta * eF;
+                        gbl -= sq * eF;
+                    }
+                }
+            }
+        });
+        const int32_t o = perm[k];
+        gx[o] = px;
+        gy[o] = py;
+        gz[o] = pz;
+        gd[o] = (Real)0.5 * rb;
+        kb = (double)kbl;
+        gb = (double)gbl;
+    }
+    if (!BATCHED) {
+        const double tk = block_sum_fixed(kb, s_w);
+        const double tg = block_sum_fixed(gb, s_w);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = tk;
+            partials[2 * blockIdx.x + 1] = tg;
+        }
+    } else {
+        const int slo = s_rng[0], shi = s_rng[1];
+        for (int t = slo; t <= shi; ++t) {
+            const bool mine = (k < n) && (s == t);
+            const double tk = block_sum_fixed(mine ? kb : 0.0, s_w);
+            const double tg = block_sum_fixed(mine ? gb : 0.0, s_w);
+            if (threadIdx.x == 0) {
+                partials[2 * ((int64_t)blockIdx.x + t)] = tk;
+                partials[2 * ((int64_t)blockIdx.x + t) + 1] = tg;
+            }
+        }
+    }
+}
+
+// One block per simulation: sum the partials of the blocks it overlaps.
+__global__ __launch_bounds__(kBlock) void k_reduce_params(const double* __restrict__ partials,
+                                                          const int64_t* __restrict__ off,
+                                                          int64_t n, const Header* __restrict__ hdr,
+                                                          double* __restrict__ out)
+{
+    __shared__ double s_w[kBlock / kWave];
+    if (hdr->error) return;
+    const int s = blockIdx.x;
+    const int64_t a0 = off ? off[s] : 0;
+    const int64_t a1 = off ? off[s + 1] : n;
+    double tk = 0.0, tg = 0.0;
+    if (a1 > a0) {
+        const int64_t c0 = a0 / kBlock, c1 = (a1 - 1) / kBlock;
+        const int64_t sh = off ? s : 0;
+        for (int64_t c = c0 + threadIdx.x; c <= c1; c += kBlock) {
+            tk += partials[2 * (c + sh)];
+            tg += partials[2 * (c + sh) + 1];
+        }
+    }
+    tk = block_sum_fixed(tk, s_w);
+    tg = block_sum_fixed(tg, s_w);
+    if (threadIdx.x == 0) {
+        out[2 * s] = tk;
+        out[2 * s + 1] = tg;
+    }
+}
+
+template <int M>
+hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                         const ms_params* p_host, const ms_params* p_dev, const void* gdx,
+                         const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
+                         double* g_params, hipStream_t s)
+{
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const Pay* pay = static_cast<const Pay*>(D.payload);
+    Pay* fb = static_cast<Pay*>(D.fbar);
+    const Real *GX = (const Real*)gdx, *GY = (const Real*)gdy, *GZ = (const Real*)gdz;
+    Real *OX = (Real*)gx, *OY = (Real*)gy, *OZ = (Real*)gz, *OD = (Real*)gd;
+    ms_params dummy{};
+    if (batched) {
+        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, D.off, B, n, dummy,
+                                                   p_dev, D.hdr, GX, GY, GZ, fb);
+        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.perm, D.geom, D.off, B, n,
+                                                     dummy, p_dev, D.hdr, OX, OY, OZ, OD,
+                                                     D.partials);
+        k_reduce_params<<<B, kBlock, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
+    } else {
+        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, nullptr, 1, n,
+                                                    *p_host, nullptr, D.hdr, GX, GY, GZ, fb);
+        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.perm, D.geom, nullptr, 1,
+                                                      n, *p_host, nullptr, D.hdr, OX, OY, OZ, OD,
+                                                      D.partials);
+        k_reduce_params<<<1, kBlock, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                           const ms_params* p_host, const ms_params* p_dev, const void* gdx,
+                           const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
+                           void* gd, double* g_params, hipStream_t s)
+{
+    switch (L.dtype) {
+    case MS_F32:
+        return backward_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
+                                     gd, g_params, s);
+    case MS_F64:
+        return backward_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
+                                     gd, g_params, s);
+    case MS_F32_POS64:
+        return backward_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx,
+                                           gy, gz, gd, g_params, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ms

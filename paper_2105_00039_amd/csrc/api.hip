@@ -1,0 +1,374 @@
+// Host side of the C ABI declared in include/mechstep.h: argument checks,
+// workspace layout, kernel launches on the caller's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <initializer_list>
+#include <vector>
+
+#include "launch.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+ms_status fail(ms_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+ms_status ok()
+{
+    g_err[0] = '\0';
+    return MS_OK;
+}
+
+ms_status check_hip(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) return fail(MS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t in_size(int dtype) { return dtype == MS_F32 ? 4 : 8; }     // positions, diameters
+size_t out_size(int dtype) { return dtype == MS_F64 ? 8 : 4; }    // displacements, gradients
+
+ms_status check_ws(const ms_workspace* ws, const char* who)
+{
+    if (!ws) return fail(MS_EINVAL, "%s: null workspace", who);
+    if (!ws->base) return fail(MS_EINVAL, "%s: workspace has no device buffer", who);
+    if (ws->dtype < MS_F32 || ws->dtype > MS_F32_POS64)
+        return fail(MS_EINVAL, "%s: workspace dtype %d unknown", who, ws->dtype);
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    if (ws->bytes < L.total)
+        return fail(MS_EINVAL, "%s: workspace holds %zu bytes, needs %zu", who, ws->bytes, L.total);
+    return MS_OK;
+}
+
+ms_status check_params(const ms_params* p, const char* who)
+{
+    if (!p) return fail(MS_EINVAL, "%s: null params", who);
+    const double v[5] = {p->kappa, p->gamma, p->dt, p->max_disp, p->adherence};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(MS_EINVAL, "%s: non-finite parameter", who);
+    if (p->dt < 0 || p->max_disp < 0 || p->adherence < 0)
+        return fail(MS_EINVAL, "%s: dt, max_disp and adherence must be >= 0", who);
+    return MS_OK;
+}
+
+ms_status check_arrays(const char* who, size_t elem, std::initializer_list<const void*> ptrs)
+{
+    for (const void* p : ptrs) {
+        if (!p) return fail(MS_EINVAL, "%s: null array", who);
+        if (!aligned(p, elem)) return fail(MS_EINVAL, "%s: array not %zu-byte aligned", who, elem);
+    }
+    return MS_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+size_t ms_workspace_bytes(int64_t max_agents, int64_t max_boxes, int32_t max_sims, ms_dtype dtype)
+{
+    if (max_agents < 0 || max_boxes < 0 || max_sims < 1) return 0;
+    return ms::make_layout(max_agents, max_boxes, max_sims, dtype).total;
+}
+
+ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t max_agents,
+                            int64_t max_boxes, int32_t max_sims, ms_dtype dtype, void* stream)
+{
+    if (!ws) return fail(MS_EINVAL, "ms_workspace_init: null workspace");
+    if (!base) return fail(MS_EINVAL, "ms_workspace_init: null buffer");
+    if (!aligned(base, 256)) return fail(MS_EINVAL, "ms_workspace_init: buffer not 256-byte aligned");
+    if (dtype < MS_F32 || dtype > MS_F32_POS64)
+        return fail(MS_EINVAL, "ms_workspace_init: unknown dtype %d", (int)dtype);
+    if (max_agents < 0 || max_agents >= 2147483647LL)
+        return fail(MS_ECAPACITY, "ms_workspace_init: max_agents must be in [0, 2^31-1)");
+    if (max_boxes < 1 || max_boxes >= 2147483647LL)
+        return fail(MS_ECAPACITY, "ms_workspace_init: max_boxes must be in [1, 2^31-1)");
+    if (max_sims < 1 || max_sims > (1 << 24))
+        return fail(MS_ECAPACITY, "ms_workspace_init: max_sims must be in [1, 2^24]");
+    const ms::Layout L = ms::make_layout(max_agents, max_boxes, max_sims, dtype);
+    if (bytes < L.total)
+        return fail(MS_EINVAL, "ms_workspace_init: %zu bytes given, %zu needed", bytes, L.total);
+    ws->base = base;
+    ws->bytes = bytes;
+    ws->max_agents = max_agents;
+    ws->max_boxes = max_boxes;
+    ws->max_sims = max_sims;
+    ws->dtype = dtype;
+    ws->n_agents = 0;
+    ws->n_sims = 0;
+    ws->built = 0;
+    return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
+}
+
+static ms_status build_common(ms_workspace* ws, const void* x, const void* y, const void* z,
+                              const void* d, int64_t n, const int64_t* off, int32_t B, double edge,
+                              const double* edges, void* stream, const char* who)
+{
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    if (n < 0) return fail(MS_EINVAL, "%s: n < 0", who);
+    if (n > ws->max_agents) return fail(MS_ECAPACITY, "%s: n = %lld exceeds max_agents = %lld", who,
+                                        (long long)n, (long long)ws->max_agents);
+    if (B > ws->max_sims) return fail(MS_ECAPACITY, "%s: %d simulations exceed max_sims = %d", who, B,
+                                      ws->max_sims);
+    if (!std::isfinite(edge)) return fail(MS_EINVAL, "%s: non-finite edge", who);
+    if (n > 0) {
+        st = check_arrays(who, in_size(ws->dtype), {x, y, z, d});
+        if (st) return st;
+    }
+    if (off && !aligned(off, 8)) return fail(MS_EINVAL, "%s: sim_offsets not 8-byte aligned", who);
+    if (edges && !aligned(edges, 8)) return fail(MS_EINVAL, "%s: edges not 8-byte aligned", who);
+    ws->n_agents = n;
+    ws->n_sims = B;
+    ws->built = off ? 2 : 1;
+    if (n == 0) return ok();
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_grid_build(L, ms::resolve(L, ws->base), x, y, z, d, n, off, B, edge,
+                                           edges, as_stream(stream)),
+                     who);
+}
+
+ms_status ms_grid_build(ms_workspace* ws, const void* x, const void* y, const void* z,
+                        const void* d, int64_t n, double edge, void* stream)
+{
+    return build_common(ws, x, y, z, d, n, nullptr, 1, edge, nullptr, stream, "ms_grid_build");
+}
+
+ms_status ms_grid_build_batched(ms_workspace* ws, const void* x, const void* y, const void* z,
+                                const void* d, const int64_t* sim_offsets, int32_t n_sims,
+                                int64_t n_total, const double* edges, void* stream)
+{
+    if (!sim_offsets) return fail(MS_EINVAL, "ms_grid_build_batched: null sim_offsets");
+    if (n_sims < 1) return fail(MS_EINVAL, "ms_grid_build_batched: n_sims < 1");
+    return build_common(ws, x, y, z, d, n_total, sim_offsets, n_sims, 0.0, edges, stream,
+                        "ms_grid_build_batched");
+}
+
+static ms_status step_common(const ms_workspace* ws, int want_built, const char* who)
+{
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    if (ws->built != want_built)
+        return fail(MS_EINVAL, "%s: workspace holds no %s grid build", who,
+                    want_built == 1 ? "plain" : "batched");
+    return MS_OK;
+}
+
+ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, void* dy, void* dz,
+                       void* stream)
+{
+    const char* who = "ms_mech_step";
+    ms_status st = step_common(ws, 1, who);
+    if (st) return st;
+    if ((st = check_params(p, who))) return st;
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
+                                      dz, as_stream(stream)),
+                     who);
+}
+
+ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, void* dx, void* dy,
+                               void* dz, void* stream)
+{
+    const char* who = "ms_mech_step_batched";
+    ms_status st = step_common(ws, 2, who);
+    if (st) return st;
+    if (!params || !aligned(params, 8)) return fail(MS_EINVAL, "%s: null or misaligned params", who);
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
+                                      params, dx, dy, dz, as_stream(stream)),
+                     who);
+}
+
+static ms_status backward_common(const ms_workspace* ws, bool batched, const ms_params* p,
+                                 const void* gdx, const void* gdy, const void* gdz, void* gx,
+                                 void* gy, void* gz, void* gd, double* g_params, void* stream,
+                                 const char* who)
+{
+    ms_status st = step_common(ws, batched ? 2 : 1, who);
+    if (st) return st;
+    if (batched) {
+        if (!p || !aligned(p, 8)) return fail(MS_EINVAL, "%s: null or misaligned params", who);
+    } else if ((st = check_params(p, who))) {
+        return st;
+    }
+    if (!g_params || !aligned(g_params, 8)) return fail(MS_EINVAL, "%s: null g_params", who);
+    const int64_t n = ws->n_agents;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    if (n == 0) return ok();
+    if ((st = check_arrays(who, out_size(ws->dtype), {gdx, gdy, gdz, gx, gy, gz, gd}))) return st;
+    return check_hip(ms::launch_backward(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
+                                         batched, batched ? nullptr : p, batched ? p : nullptr, gdx,
+                                         gdy, gdz, gx, gy, gz, gd, g_params, as_stream(stream)),
+                     who);
+}
+
+ms_status ms_mech_step_backward(const ms_workspace* ws, const ms_params* p, const void* gdx,
+                                const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
+                                void* gd, double* g_params, void* stream)
+{
+    return backward_common(ws, false, p, gdx, gdy, gdz, gx, gy, gz, gd, g_params, stream,
+                           "ms_mech_step_backward");
+}
+
+ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
+                                        const void* gdx, const void* gdy, const void* gdz, void* gx,
+                                        void* gy, void* gz, void* gd, double* g_params,
+                                        void* stream)
+{
+    return backward_common(ws, true, params, gdx, gdy, gdz, gx, gy, gz, gd, g_params, stream,
+                           "ms_mech_step_backward_batched");
+}
+
+ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy, const void* dz,
+                       int64_t n, ms_dtype dtype, void* stream)
+{
+    const char* who = "ms_integrate";
+    if (n < 0) return fail(MS_EINVAL, "%s: n < 0", who);
+    if (dtype < MS_F32 || dtype > MS_F32_POS64) return fail(MS_EINVAL, "%s: unknown dtype", who);
+    if (n == 0) return ok();
+    ms_status st = check_arrays(who, in_size(dtype), {x, y, z});
+    if (st) return st;
+    if ((st = check_arrays(who, out_size(dtype), {dx, dy, dz}))) return st;
+    return check_hip(ms::launch_integrate(x, y, z, dx, dy, dz, n, dtype, as_stream(stream)), who);
+}
+
+ms_status ms_grid_get(const ms_workspace* ws, ms_grid_info* info, int32_t* box_id,
+                      int32_t* box_start, int32_t* perm, void* stream)
+{
+    const char* who = "ms_grid_get";
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    if (!ws->built) return fail(MS_EINVAL, "%s: no grid build", who);
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    const ms::Dev D = ms::resolve(L, ws->base);
+    hipStream_t s = as_stream(stream);
+    const int64_t n = ws->n_agents;
+    const int32_t B = ws->n_sims;
+    if (n == 0) {
+        if (info) {
+            for (int b = 0; b < B; ++b) {
+                std::memset(&info[b], 0, sizeof(ms_grid_info));
+            }
+        }
+        return ok();
+    }
+    ms::Header h;
+    hipError_t e = hipMemcpyAsync(&h, D.hdr, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((st = check_hip(e, who))) return st;
+    if (info) {
+        std::vector<ms::SimGeom> g(B);
+        std::vector<int64_t> off(B + 1);
+        e = hipMemcpyAsync(g.data(), D.geom, sizeof(ms::SimGeom) * B, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && ws->built == 2)
+            e = hipMemcpyAsync(off.data(), D.off, 8 * (B + 1), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if ((st = check_hip(e, who))) return st;
+        if (ws->built == 1) { off[0] = 0; off[1] = n; }
+        for (int b = 0; b < B; ++b) {
+            ms_grid_info& I = info[b];
+            for (int k = 0; k < 3; ++k) { I.origin[k] = g[b].origin[k]; I.dims[k] = g[b].dims[k]; }
+            I.edge = g[b].edge;
+            I.error = g[b].error | (int32_t)h.error;
+            I.n_boxes = g[b].n_boxes;
+            I.box_base = g[b].box_base;
+            I.n_agents = off[b + 1] - off[b];
+        }
+    }
+    if (h.error) return fail(MS_EINVAL, "%s: the last build failed on the device (error bits %u)", who,
+                             h.error);
+    if (box_id) e = hipMemcpyAsync(box_id, D.box_id, 4 * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && box_start)
+        e = hipMemcpyAsync(box_start, D.start, 4 * (h.total_boxes + 1), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && perm) e = hipMemcpyAsync(perm, D.perm, 4 * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return check_hip(e, who);
+}
+
+ms_status ms_neighbors(const ms_workspace* ws, int32_t* counts, int64_t* offsets, int32_t* list,
+                       int64_t cap, int64_t* total, void* stream)
+{
+    const char* who = "ms_neighbors";
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    if (!ws->built) return fail(MS_EINVAL, "%s: no grid build", who);
+    if (!offsets || !aligned(offsets, 8)) return fail(MS_EINVAL, "%s: null offsets", who);
+    const int64_t n = ws->n_agents;
+    if (n > 0 && (!counts || !aligned(counts, 4))) return fail(MS_EINVAL, "%s: null counts", who);
+    st = ms_device_status(ws, stream);
+    if (st) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    const ms::Dev D = ms::resolve(L, ws->base);
+    hipStream_t s = as_stream(stream);
+    const bool batched = ws->built == 2;
+    int64_t tot = 0;
+    hipError_t e = hipSuccess;
+    if (n == 0) {
+        e = hipMemcpyAsync(offsets, &tot, 8, hipMemcpyHostToDevice, s);
+    } else {
+        e = ms::launch_neighbors_count(L, D, n, ws->n_sims, batched, counts, offsets, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&tot, offsets + n, 8, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((st = check_hip(e, who))) return st;
+    if (total) *total = tot;
+    if (!list) return ok();
+    if (cap < tot) return fail(MS_ECAPACITY, "%s: list holds %lld, needs %lld", who, (long long)cap,
+                               (long long)tot);
+    if (n == 0) return ok();
+    if (!aligned(list, 4)) return fail(MS_EINVAL, "%s: list not aligned", who);
+    e = ms::launch_neighbors_fill(L, D, n, ws->n_sims, batched, offsets, list, s);
+    return check_hip(e, who);
+}
+
+ms_status ms_device_status(const ms_workspace* ws, void* stream)
+{
+    const char* who = "ms_device_status";
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    const ms::Dev D = ms::resolve(L, ws->base);
+    hipStream_t s = as_stream(stream);
+    uint32_t err = 0;
+    hipError_t e = hipSuccess;
+    if (ws->built && ws->n_agents > 0) e = hipMemcpyAsync(&err, &D.hdr->error, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if ((st = check_hip(e, who))) return st;
+    if (err & (ms::ERR_NONFINITE | ms::ERR_NEGDIAM))
+        return fail(MS_EINPUT, "non-finite position/diameter or negative diameter (bits %u)", err);
+    if (err & ms::ERR_CAPACITY) return fail(MS_ECAPACITY, "more boxes than the workspace holds (bits %u)", err);
+    if (err) return fail(MS_EINVAL, "edge or simulation offsets invalid (bits %u)", err);
+    return ok();
+}
+
+ms_status ms_copy_probe(void* dst, const void* src, size_t bytes, void* stream)
+{
+    const char* who = "ms_copy_probe";
+    if (!dst || !src || !aligned(dst, 16) || !aligned(src, 16) || bytes % 16)
+        return fail(MS_EINVAL, "%s: pointers must be 16-byte aligned and bytes a multiple of 16", who);
+    if (bytes == 0) return ok();
+    return check_hip(ms::launch_copy_probe(dst, src, bytes, as_stream(stream)), who);
+}
+
+const char* ms_last_error(void) { return g_err; }
+
+}  // extern "C"

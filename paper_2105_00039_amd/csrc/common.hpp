@@ -1,0 +1,215 @@
+// Shared device/host definitions of the mechstep library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "mechstep.h"
+
+namespace ms {
+
+constexpr int kBlock = 256;           // threads per block for every per-agent kernel
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr int kScanItems = 8;         // items per thread in the box scan
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kBoundsChunk = kBlock * 16;   // agents per block in the bounds pass
+
+// Device error bits (ms_grid_info.error and the workspace error word).
+enum : uint32_t {
+    ERR_NONFINITE = 1u,   // non-finite position or diameter
+    ERR_NEGDIAM = 2u,     // negative diameter
+    ERR_EDGE = 4u,        // edge <= 0, non-finite, or below the largest diameter
+    ERR_CAPACITY = 8u,    // more boxes than the workspace holds (or int32 overflow)
+};
+
+// Workspace header (first 256 bytes of the device buffer).
+struct Header {
+    uint32_t error;        // error bits of the last build, rewritten by every build
+    uint32_t epoch;        // build counter (1 .. 2^30-1), tags the scan tile flags
+    uint32_t scan_ticket;  // dynamic tile index of the look-back scan
+    uint32_t n_sims;
+    int64_t total_boxes;   // boxes over all simulations of the last build
+    int64_t n_agents;
+    int64_t need_boxes;    // boxes the last build asked for (even when over capacity)
+    uint8_t pad[256 - 40];
+};
+static_assert(sizeof(Header) == 256, "header size");
+
+// Per-simulation grid geometry (64 bytes).
+struct SimGeom {
+    double origin[3];
+    double edge;
+    int32_t dims[3];
+    int32_t error;
+    int32_t box_base;
+    int32_t pad;
+    int64_t n_boxes;
+};
+static_assert(sizeof(SimGeom) == 64, "geom size");
+
+// Per-simulation bounds accumulators: order-preserving integer encodings of
+// min x,y,z, max x,y,z, max d, and an error-flag word.
+struct SimAcc {
+    unsigned long long lo[3];
+    unsigned long long hi[3];
+    unsigned long long dmax;
+    unsigned long long flags;
+};
+static_assert(sizeof(SimAcc) == 64, "acc size");
+
+struct alignas(16) F4 { float x, y, z, w; };
+struct alignas(32) D4 { double x, y, z, w; };
+
+template <int M> struct Mode;
+template <> struct Mode<MS_F32>       { using In = float;  using Real = float;  using Pay = F4; };
+template <> struct Mode<MS_F64>       { using In = double; using Real = double; using Pay = D4; };
+template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  using Pay = F4; };
+
+// Byte offsets of every region of the workspace buffer.
+struct Layout {
+    size_t hdr, acc, geom, off, box_id, slot, count, start, flags, perm_tmp, perm, payload, fbar,
+        partials, scratch64, total;
+    int64_t max_agents, max_boxes, n_scan_tiles, n_part;
+    int32_t max_sims;
+    int32_t dtype;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sims, int32_t dtype)
+{
+    Layout L{};
+    L.max_agents = max_agents;
+    L.max_boxes = max_boxes;
+    L.max_sims = max_sims;
+    L.dtype = dtype;
+    const size_t real = (dtype == MS_F64) ? 8 : 4;
+    const size_t pay = (dtype == MS_F64) ? sizeof(D4) : sizeof(F4);
+    const int64_t na = max_agents > 0 ? max_agents : 1;
+    const int64_t nblk = (na + kBlock - 1) / kBlock;
+    L.n_scan_tiles = (max_boxes + 1 + kScanTile - 1) / kScanTile;
+    L.n_part = nblk + max_sims + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    L.hdr = take(sizeof(Header));
+    L.acc = take(sizeof(SimAcc) * (size_t)max_sims);
+    L.geom = take(sizeof(SimGeom) * (size_t)max_sims);
+    L.off = take(8 * (size_t)(max_sims + 1));
+    L.box_id = take(4 * (size_t)na);
+    L.slot = take(4 * (size_t)na);
+    L.count = take(4 * (size_t)(max_boxes + 1));
+    L.start = take(4 * (size_t)(max_boxes + 2));
+    L.flags = take(8 * (size_t)L.n_scan_tiles);
+    L.perm_tmp = take(4 * (size_t)na);
+    L.perm = take(4 * (size_t)na);
+    L.payload = take(pay * (size_t)na);
+    L.fbar = take(pay * (size_t)na);
+    L.partials = take(16 * (size_t)L.n_part);
+    // int64 scratch for the neighbour-offset scan: one entry per scan tile of n+1 items
+    L.scratch64 = take(8 * (size_t)((na + 1 + kScanTile - 1) / kScanTile + 1));
+    (void)real;
+    L.total = o;
+    return L;
+}
+
+// Device pointers of every region.
+struct Dev {
+    Header* hdr;
+    SimAcc* acc;
+    SimGeom* geom;
+    int64_t* off;
+    int32_t* box_id;
+    int32_t* slot;
+    int32_t* count;
+    int32_t* start;
+    unsigned long long* flags;
+    int32_t* perm_tmp;
+    int32_t* perm;
+    void* payload;
+    void* fbar;
+    double* partials;
+    long long* scratch64;
+};
+
+inline Dev resolve(const Layout& L, void* base)
+{
+    char* b = static_cast<char*>(base);
+    Dev d;
+    d.hdr = reinterpret_cast<Header*>(b + L.hdr);
+    d.acc = reinterpret_cast<SimAcc*>(b + L.acc);
+    d.geom = reinterpret_cast<SimGeom*>(b + L.geom);
+    d.off = reinterpret_cast<int64_t*>(b + L.off);
+    d.box_id = reinterpret_cast<int32_t*>(b + L.box_id);
+    d.slot = reinterpret_cast<int32_t*>(b + L.slot);
+    d.count = reinterpret_cast<int32_t*>(b + L.count);
+    d.start = reinterpret_cast<int32_t*>(b + L.start);
+    d.flags = reinterpret_cast<unsigned long long*>(b + L.flags);
+    d.perm_tmp = reinterpret_cast<int32_t*>(b + L.perm_tmp);
+    d.perm = reinterpret_cast<int32_t*>(b + L.perm);
+    d.payload = b + L.payload;
+    d.fbar = b + L.fbar;
+    d.partials = reinterpret_cast<double*>(b + L.partials);
+    d.scratch64 = reinterpret_cast<long long*>(b + L.scratch64);
+    return d;
+}
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ unsigned long long enc_f64(double v)
+{
+    unsigned long long u = __double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double dec_f64(unsigned long long k)
+{
+    unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double(u);
+}
+
+// Box index along one axis: floor((p - o)/e) in FP64, clamped to [0, dim-1].
+__device__ __forceinline__ int axis_index(double p, double o, double e, int dim)
+{
+    double q = floor((p - o) / e);
+    int i = (q > 0.0) ? (int)q : 0;
+    return i < dim - 1 ? i : dim - 1;
+}
+
+// Simulation owning index k of a concatenation with offsets off[0..B]:
+// the largest s < B with off[s] <= k, searched in [lo, hi).
+__device__ __forceinline__ int find_sim(const int64_t* __restrict__ off, int lo, int hi, int64_t k)
+{
+    // invariant: off[lo] <= k, answer in [lo, hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) { T w = __shfl_xor(v, o); v = w < v ? w : v; }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) { T w = __shfl_xor(v, o); v = w > v ? w : v; }
+    return v;
+}
+
+}  // namespace ms

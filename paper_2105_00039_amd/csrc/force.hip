@@ -1,0 +1,329 @@
+// Forward mechanical step (Section III, Eq. 1 and the displacement rule),
+// position update, neighbour-set export and the bandwidth probe.
+//
+// k_force: one lane per agent in box-sorted order (the paper's GPU kernels
+// also give each thread one agent).  Consecutive lanes hold agents of the same
+// or neighbouring boxes, so a wavefront walks nearly the same 9 runs and its
+// candidate loads are served by L1/L2.  The force is summed in registers in
+// ascending (box, input index) order; the displacement is written to the
+// agent's input position through perm.
+#include "gather.hpp"
+#include "launch.hpp"
+
+namespace ms {
+namespace {
+
+template <int M, bool BATCHED>
+__global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
+                                                  const int32_t* __restrict__ start,
+                                                  const int32_t* __restrict__ perm,
+                                                  const SimGeom* __restrict__ geom,
+                                                  const int64_t* __restrict__ off, int32_t B,
+                                                  int64_t n, ms_params p1,
+                                                  const ms_params* __restrict__ pB,
+                                                  const Header* __restrict__ hdr,
+                                                  typename Mode<M>::Real* __restrict__ dx,
+                                                  typename Mode<M>::Real* __restrict__ dy,
+                                                  typename Mode<M>::Real* __restrict__ dz)
+{
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    if (hdr->error) return;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t k = k0 + threadIdx.x;
+    int s = 0;
+    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (k >= n) return;
+    const SimGeom g = geom[s];
+    const ms_params P = BATCHED ? pB[s] : p1;
+    const Pay pi = pay[k];
+    const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
+    Real fx, fy, fz;
+    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, fx, fy, fz);
+    Real ddx, ddy, ddz;
+    displacement<Real>(fx, fy, fz, (Real)P.dt, (Real)P.max_disp, (Real)P.adherence, ddx, ddy, ddz);
+    const int32_t o = perm[k];
+    dx[o] = ddx;
+    dy[o] = ddy;
+    dz[o] = ddz;
+}
+
+template <typename PT, typename DT>
+__global__ __launch_bounds__(kBlock) void k_integrate(PT* __restrict__ x, PT* __restrict__ y,
+                                                      PT* __restrict__ z,
+                                                      const DT* __restrict__ dx,
+                                                      const DT* __restrict__ dy,
+                                                      const DT* __restrict__ dz, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    x[i] += (PT)dx[i];
+    y[i] += (PT)dy[i];
+    z[i] += (PT)dz[i];
+}
+
+// Neighbour sets with the FP64 predicate |p_j - p_i|^2 < edge^2, the square
+// evaluated as (ux*ux + uy*uy) + uz*uz with no fused multiply-add so that it
+// is reproducible bit for bit.
+template <int M, bool BATCHED, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_neighbors(const typename Mode<M>::Pay* __restrict__ pay,
+                                                      const int32_t* __restrict__ start,
+                                                      const int32_t* __restrict__ perm,
+                                                      const SimGeom* __restrict__ geom,
+                                                      const int64_t* __restrict__ off, int32_t B,
+                                                      int64_t n, const Header* __restrict__ hdr,
+                                                      int32_t* __restrict__ counts,
+                                                      const int64_t* __restrict__ offsets,
+                                                      int32_t* __restrict__ list)
+{
+#pragma clang fp contract(off)
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    if (hdr->error) return;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t k = k0 + threadIdx.x;
+    int s = 0;
+    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (k >= n) return;
+    const SimGeom g = geom[s];
+    const Pay pi = pay[k];
+    const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
+    const double xi = (double)pi.x, yi = (double)pi.y, zi = (double)pi.z;
+    const double e2 = g.edge * g.edge;
+    const int32_t me = perm[k];
+    int64_t cnt = 0;
+    const int64_t base = FILL ? offsets[me] : 0;
+    for_each_run(g, c, start, [&](int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            if (j == (int)k) continue;
+            const Pay q = pay[j];
+            const double ux = (double)q.x - xi, uy = (double)q.y - yi, uz = (double)q.z - zi;
+            const double d2 = (ux * ux + uy * uy) + uz * uz;
+            if (d2 < e2) {
+                if (FILL) list[base + cnt] = perm[j];
+                ++cnt;
+            }
+        }
+    });
+    if (!FILL) counts[me] = (int32_t)cnt;
+}
+
+// Three-phase exclusive scan of int32 counts [n] into int64 offsets [n+1].
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const int32_t* __restrict__ in, int64_t n,
+                                                      long long* __restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    long long v = 0;
+    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+        const int64_t i = base + k;
+        if (i < n) v += in[i];
+    }
+    v = wave_sum<long long>(v);
+    __shared__ long long s_w[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(long long* sums, int64_t ntiles)
+{
+    // single block, sequential over chunks of kBlock tiles
+    __shared__ long long s_v[kBlock];
+    long long running = 0;
+    for (int64_t c = 0; c < ntiles; c += kBlock) {
+        const int64_t t = c + threadIdx.x;
+        const long long v = t < ntiles ? sums[t] : 0;
+        s_v[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            long long a = threadIdx.x >= (unsigned)o ? s_v[threadIdx.x - o] : 0;
+            __syncthreads();
+            s_v[threadIdx.x] += a;
+            __syncthreads();
+        }
+        const long long inc = s_v[threadIdx.x];
+        const long long tot = s_v[kBlock - 1];
+        if (t < ntiles) sums[t] = running + inc - v;
+        running += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[ntiles] = running;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_scan(const int32_t* __restrict__ in, int64_t n,
+                                                      const long long* __restrict__ sums,
+                                                      int64_t* __restrict__ out)
+{
+    __shared__ long long s_v[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long v[kScanItems];
+    long long tsum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        tsum += v[k];
+    }
+    s_v[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        long long a = threadIdx.x >= (unsigned)o ? s_v[threadIdx.x - o] : 0;
+        __syncthreads();
+        s_v[threadIdx.x] += a;
+        __syncthreads();
+    }
+    long long run = sums[blockIdx.x] + s_v[threadIdx.x] - tsum;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i <= n) out[i] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                 int64_t n4)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+template <int M>
+hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                      const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
+                      void* dz, hipStream_t s)
+{
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const Pay* pay = static_cast<const Pay*>(D.payload);
+    Real* X = static_cast<Real*>(dx);
+    Real* Y = static_cast<Real*>(dy);
+    Real* Z = static_cast<Real*>(dz);
+    if (batched) {
+        ms_params dummy{};
+        k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, D.off, B, n, dummy,
+                                                p_dev, D.hdr, X, Y, Z);
+    } else {
+        k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, nullptr, 1, n,
+                                                 *p_host, nullptr, D.hdr, X, Y, Z);
+    }
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                    int32_t* counts, int64_t* offsets, int32_t* list, bool fill, hipStream_t s)
+{
+    using Pay = typename Mode<M>::Pay;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const Pay* pay = static_cast<const Pay*>(D.payload);
+    const int64_t* off = batched ? D.off : nullptr;
+    if (!fill) {
+        if (batched)
+            k_neighbors<M, true, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, B,
+                                                               n, D.hdr, counts, nullptr, nullptr);
+        else
+            k_neighbors<M, false, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, 1,
+                                                                n, D.hdr, counts, nullptr, nullptr);
+        const int64_t ntiles = (n + 1 + kScanTile - 1) / kScanTile;
+        k_tile_sums<<<(unsigned)ntiles, kBlock, 0, s>>>(counts, n, D.scratch64);
+        k_scan_sums<<<1, kBlock, 0, s>>>(D.scratch64, ntiles);
+        k_tile_scan<<<(unsigned)ntiles, kBlock, 0, s>>>(counts, n, D.scratch64, offsets);
+    } else {
+        if (batched)
+            k_neighbors<M, true, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, B, n,
+                                                              D.hdr, nullptr, offsets, list);
+        else
+            k_neighbors<M, false, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, 1,
+                                                               n, D.hdr, nullptr, offsets, list);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                        const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
+                        void* dz, hipStream_t s)
+{
+    switch (L.dtype) {
+    case MS_F32: return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
+    case MS_F64: return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
+    case MS_F32_POS64:
+        return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
+                            const void* dz, int64_t n, int dtype, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    switch (dtype) {
+    case MS_F32:
+        k_integrate<float, float><<<nb, kBlock, 0, s>>>(
+            (float*)x, (float*)y, (float*)z, (const float*)dx, (const float*)dy, (const float*)dz, n);
+        break;
+    case MS_F64:
+        k_integrate<double, double><<<nb, kBlock, 0, s>>>((double*)x, (double*)y, (double*)z,
+                                                          (const double*)dx, (const double*)dy,
+                                                          (const double*)dz, n);
+        break;
+    case MS_F32_POS64:
+        k_integrate<double, float><<<nb, kBlock, 0, s>>>((double*)x, (double*)y, (double*)z,
+                                                         (const float*)dx, (const float*)dy,
+                                                         (const float*)dz, n);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_neighbors_count(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                                  int32_t* counts, int64_t* offsets, hipStream_t s)
+{
+    switch (L.dtype) {
+    case MS_F32: return nbr_mode<MS_F32>(L, D, n, B, batched, counts, offsets, nullptr, false, s);
+    case MS_F64: return nbr_mode<MS_F64>(L, D, n, B, batched, counts, offsets, nullptr, false, s);
+    case MS_F32_POS64:
+        return nbr_mode<MS_F32_POS64>(L, D, n, B, batched, counts, offsets, nullptr, false, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_neighbors_fill(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                                 const int64_t* offsets, int32_t* list, hipStream_t s)
+{
+    int64_t* o = const_cast<int64_t*>(offsets);
+    switch (L.dtype) {
+    case MS_F32: return nbr_mode<MS_F32>(L, D, n, B, batched, nullptr, o, list, true, s);
+    case MS_F64: return nbr_mode<MS_F64>(L, D, n, B, batched, nullptr, o, list, true, s);
+    case MS_F32_POS64:
+        return nbr_mode<MS_F32_POS64>(L, D, n, B, batched, nullptr, o, list, true, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    const int64_t n4 = (int64_t)(bytes / 16);
+    int64_t blocks = (n4 + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_copy<<<(unsigned)blocks, kBlock, 0, s>>>(static_cast<const uint4*>(src),
+                                                static_cast<uint4*>(dst), n4);
+    return hipGetLastError();
+}
+
+}  // namespace ms

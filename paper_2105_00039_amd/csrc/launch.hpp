@@ -1,0 +1,40 @@
+// Host-side launchers of the mechstep kernels (one translation unit each).
+#pragma once
+
+#include "common.hpp"
+
+namespace ms {
+
+// Clear the device state of a fresh workspace.
+hipError_t launch_init(const Layout& L, const Dev& D, hipStream_t s);
+
+// Uniform grid: bounds -> geometry -> count -> scan -> scatter -> rank.
+// off == nullptr means one simulation of n agents (B must be 1).
+hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const void* y,
+                             const void* z, const void* d, int64_t n, const int64_t* off,
+                             int32_t B, double edge, const double* edges, hipStream_t s);
+
+// Forward step.  Single: p_host valid, off == nullptr.  Batched: p_dev valid.
+hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                        const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
+                        void* dz, hipStream_t s);
+
+hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                           const ms_params* p_host, const ms_params* p_dev, const void* gdx,
+                           const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
+                           void* gd, double* g_params, hipStream_t s);
+
+hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
+                            const void* dz, int64_t n, int dtype, hipStream_t s);
+
+// Neighbour export: counts + offsets (phase 1), list (phase 2).
+hipError_t launch_neighbors_count(const Layout& L, const Dev& D, int64_t n, int32_t B,
+                                  bool batched, int32_t* counts, int64_t* offsets, hipStream_t s);
+hipError_t launch_neighbors_fill(const Layout& L, const Dev& D, int64_t n, int32_t B,
+                                 bool batched, const int64_t* offsets, int32_t* list,
+                                 hipStream_t s);
+
+// Gather of per-agent box ids in caller order for export.
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace ms

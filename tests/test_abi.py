@@ -1,0 +1,92 @@
+"""The C ABI library loads and exports every function include/mechstep.h
+declares; host-side argument checks reject bad calls before any device work.
+Runs without a GPU: no call here reaches a kernel launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mechstep.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ms_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2105_00039_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build(force=False)
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2105_00039_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_workspace_bytes_is_host_only(lib):
+    from paper_2105_00039_amd import _lib
+    a = lib.ms_workspace_bytes(1000, 5000, 1, _lib.MS_F32)
+    b = lib.ms_workspace_bytes(1000, 5000, 1, _lib.MS_F64)
+    c = lib.ms_workspace_bytes(2000, 5000, 1, _lib.MS_F32)
+    assert 0 < a < b and a < c
+    assert a % 256 == 0
+    assert lib.ms_workspace_bytes(-1, 10, 1, _lib.MS_F32) == 0
+    assert lib.ms_workspace_bytes(10, 10, 0, _lib.MS_F32) == 0
+
+
+def test_host_validation_errors(lib):
+    from paper_2105_00039_amd import _lib
+    ws = _lib.ms_workspace()
+    # null workspace / buffer
+    assert lib.ms_workspace_init(None, ctypes.c_void_p(256), 1 << 20, 10, 10, 1, 0, None) == _lib.MS_EINVAL
+    assert b"null" in lib.ms_last_error()
+    assert lib.ms_workspace_init(ctypes.byref(ws), None, 1 << 20, 10, 10, 1, 0, None) == _lib.MS_EINVAL
+    # misaligned buffer
+    assert lib.ms_workspace_init(ctypes.byref(ws), ctypes.c_void_p(8), 1 << 20, 10, 10, 1, 0, None) == _lib.MS_EINVAL
+    assert b"aligned" in lib.ms_last_error()
+    # too small
+    assert lib.ms_workspace_init(ctypes.byref(ws), ctypes.c_void_p(256), 64, 10, 10, 1, 0, None) == _lib.MS_EINVAL
+    # bad dtype / capacities
+    assert lib.ms_workspace_init(ctypes.byref(ws), ctypes.c_void_p(256), 1 << 20, 10, 10, 1, 7, None) == _lib.MS_EINVAL
+    assert lib.ms_workspace_init(ctypes.byref(ws), ctypes.c_void_p(256), 1 << 40, 1 << 31, 10, 1, 0, None) == _lib.MS_ECAPACITY
+    # step calls on a workspace without a buffer
+    p = _lib.ms_params(2, 1, 0.01, 3, 0)
+    assert lib.ms_grid_build(None, None, None, None, None, 10, 0.0, None) == _lib.MS_EINVAL
+    assert lib.ms_mech_step(ctypes.byref(ws), ctypes.byref(p), None, None, None, None) == _lib.MS_EINVAL
+    # integrate / probe argument checks
+    assert lib.ms_integrate(None, None, None, None, None, None, -1, 0, None) == _lib.MS_EINVAL
+    assert lib.ms_integrate(None, None, None, None, None, None, 5, 9, None) == _lib.MS_EINVAL
+    assert lib.ms_integrate(None, None, None, None, None, None, 5, 0, None) == _lib.MS_EINVAL
+    assert lib.ms_copy_probe(ctypes.c_void_p(16), ctypes.c_void_p(32), 17, None) == _lib.MS_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the header structs have the C compiler's sizes and offsets."""
+    import subprocess
+    from paper_2105_00039_amd import _lib
+    prog = tmp_path / "sizes.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "mechstep.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ms_params),'
+        ' sizeof(ms_grid_info), sizeof(ms_workspace), offsetof(ms_grid_info, n_boxes),'
+        ' offsetof(ms_workspace, dtype), offsetof(ms_workspace, n_sims), offsetof(ms_workspace, built));'
+        'return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(_lib.ms_params), ctypes.sizeof(_lib.ms_grid_info),
+            ctypes.sizeof(_lib.ms_workspace), _lib.ms_grid_info.n_boxes.offset,
+            _lib.ms_workspace.dtype.offset, _lib.ms_workspace.n_sims.offset,
+            _lib.ms_workspace.built.offset]
+    assert got == want

@@ -1,0 +1,193 @@
+"""GPU reverse-mode derivative (ms_mech_step_backward and the autograd layer)
+against the oracle's adjoint, finite differences of the GPU FP64 forward, and
+checkpoint-interval invariance.
+
+Tolerances (the target sets none; derived from the arithmetic): configurations
+keep every pair within the radius at |delta| > 1e-2 and away from the length
+bound, where ds/ddelta is bounded; FP64 results agree with the oracle to 1e-10
+of the largest gradient component, FP32 to 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2105_00039_amd as ms
+from paper_2105_00039_amd import autograd as msa
+from paper_2105_00039_amd import workloads
+from helpers import NP_IN, oracle_inputs
+
+pytestmark = pytest.mark.gpu
+
+REL = {"f64": 1e-10, "f32": 1e-3, "f32_pos64": 1e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ms._lib.load()
+
+
+def smooth_pop(n, nbrs, seed, params, mode="f64", gap=1e-2, steps=1):
+    """A population kept away from the kinks of the step map over a
+    ``steps``-step oracle trajectory: every pair within the radius has
+    |delta| > gap and every agent has ||v| - m| > 1e-3 m, in the precision the
+    GPU path sees.  Agents of offending pairs are removed until none is left."""
+    pop = workloads.uniform(n, mean_neighbors=nbrs, seed=seed)
+    keep = np.ones(pop.n, dtype=bool)
+    arrs0 = [np.asarray(a) for a in pop.arrays()]
+    for _ in range(100):
+        arrs = [a[keep] for a in arrs0]
+        o = list(oracle_inputs(arrs, mode))
+        bad = np.zeros(len(arrs[0]), dtype=bool)
+        traj = oracle.rollout(*o, params, steps)
+        for p in traj[:-1] if steps > 0 else traj:
+            q = (p[:, 0], p[:, 1], p[:, 2], o[3])
+            c, off, lst = oracle.neighbors(*q)
+            i = np.repeat(np.arange(len(c)), c)
+            l = np.sqrt((q[0][i] - q[0][lst]) ** 2 + (q[1][i] - q[1][lst]) ** 2 + (q[2][i] - q[2][lst]) ** 2)
+            delta = q[3][i] / 2 + q[3][lst] / 2 - l
+            near = np.abs(delta) < gap
+            bad[np.minimum(i[near], lst[near])] = True
+            F, _ = oracle.step(*q, params)
+            v = params["dt"] * np.linalg.norm(F, axis=1)
+            bad |= np.abs(v - params["max_disp"]) < 1e-3 * params["max_disp"]
+        if not bad.any():
+            return workloads.Population(*arrs)
+        idx = np.nonzero(keep)[0]
+        keep[idx[bad]] = False
+    raise RuntimeError("no smooth population")
+
+
+def dev(arrs, mode):
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(NP_IN[mode]))).cuda() for a in arrs]
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32", "f32_pos64"])
+@pytest.mark.parametrize("clamp", [False, True])
+def test_backward_matches_oracle_adjoint(mode, clamp):
+    prm = dict(kappa=2.0, gamma=1.0, dt=0.05 if clamp else 0.01,
+               max_disp=0.02 if clamp else 3.0, adherence=0.0)
+    pop = smooth_pop(1500, 15.0, 10 if clamp else 30, prm, mode)
+    arrs = pop.arrays()
+    o = oracle_inputs(arrs, mode)
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=(pop.n, 3))
+    if mode != "f64":
+        g = g.astype(np.float32).astype(np.float64)
+    ws = ms.Workspace(pop.n, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t)
+    gt = [torch.from_numpy(np.ascontiguousarray(g[:, k])).to(ws.out_dtype).cuda() for k in range(3)]
+    gx, gy, gz, gd, gkg = ms.mech_step_backward(ws, prm, *gt)
+    ms.device_status(ws)
+    gp_o, gd_o, gkg_o = oracle.step_adjoint(*o, prm, g)
+    gp = np.stack([a.cpu().numpy().astype(np.float64) for a in (gx, gy, gz)], axis=1)
+    tol = REL[mode]
+    assert np.abs(gp - gp_o).max() <= tol * np.abs(gp_o).max()
+    assert np.abs(gd.cpu().numpy() - gd_o).max() <= tol * np.abs(gd_o).max()
+    np.testing.assert_allclose(gkg.cpu().numpy(), gkg_o, rtol=tol * 10, atol=0)
+    if clamp:
+        F, _ = oracle.step(*o, prm)
+        assert np.sum(prm["dt"] * np.linalg.norm(F, axis=1) > prm["max_disp"]) > 50
+    # bitwise repeatable
+    again = ms.mech_step_backward(ws, prm, *gt)
+    for a, b in zip((gx, gy, gz, gd, gkg), again):
+        assert torch.equal(a, b)
+
+
+def test_single_step_autograd_f64():
+    prm = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+    pop = smooth_pop(500, 15.0, 50, prm)
+    t = [a.requires_grad_(True) for a in dev(pop.arrays(), "f64")]
+    kap = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
+    gam = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    ws = ms.Workspace(pop.n, dtype="f64")
+    rest = dict(dt=0.01, max_disp=3.0, adherence=0.0)
+    D = msa.mech_step_fn(*t, kap, gam, ws, rest)
+    w = torch.linspace(-1, 1, pop.n, dtype=torch.float64, device="cuda")
+    L = (D[0] * w).sum() + (D[1] * w * w).sum() - D[2].sum()
+    L.backward()
+    g = np.stack([w.cpu().numpy(), (w * w).cpu().numpy(), -np.ones(pop.n)], axis=1)
+    gp_o, gd_o, gkg_o = oracle.step_adjoint(*pop.arrays(), prm, g)
+    for k in range(3):
+        np.testing.assert_allclose(t[k].grad.cpu().numpy(), gp_o[:, k], rtol=0,
+                                   atol=1e-10 * np.abs(gp_o).max())
+    np.testing.assert_allclose(t[3].grad.cpu().numpy(), gd_o, rtol=0, atol=1e-10 * np.abs(gd_o).max())
+    np.testing.assert_allclose([kap.grad.item(), gam.grad.item()], gkg_o, rtol=1e-9)
+
+
+def _rollout_loss(mode, pop, tgt, steps, K, rest, kap=2.0, gam=1.0, ws=None):
+    t = [a.requires_grad_(True) for a in dev(pop.arrays(), mode)]
+    k = torch.tensor(kap, dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(gam, dtype=torch.float64, requires_grad=True)
+    ws = ws or ms.Workspace(pop.n, dtype=mode)
+    px, py, pz = msa.rollout(*t, k, g, ws, rest, steps, K)
+    tx, ty, tz = (torch.from_numpy(np.asarray(a).astype(NP_IN[mode])).cuda() for a in tgt)
+    L = ((px - tx) ** 2 + (py - ty) ** 2 + (pz - tz) ** 2).mean()
+    L.backward()
+    return L.item(), [a.grad.clone() for a in t], k.grad.item(), g.grad.item()
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32", "f32_pos64"])
+def test_rollout_checkpoint_interval_invariance(mode):
+    rest = dict(dt=0.05, max_disp=3.0, adherence=0.0)
+    pop = workloads.uniform(3000, mean_neighbors=12.0, seed=3)
+    tgt = workloads.targets(pop, seed=3)
+    r1 = _rollout_loss(mode, pop, tgt, 20, 1, rest)
+    r10 = _rollout_loss(mode, pop, tgt, 20, 10, rest)
+    assert r1[0] == r10[0]
+    for a, b in zip(r1[1], r10[1]):
+        assert torch.equal(a, b)
+    assert r1[2] == r10[2] and r1[3] == r10[3]
+
+
+def test_rollout_gradient_matches_oracle_f64():
+    prm = dict(kappa=2.0, gamma=1.0, dt=0.05, max_disp=3.0, adherence=0.0)
+    rest = dict(dt=0.05, max_disp=3.0, adherence=0.0)
+    pop = smooth_pop(800, 12.0, 70, prm, gap=1e-2, steps=6)
+    tgt = workloads.targets(pop, seed=1)
+    steps = 6
+    L, gp, gk, gg = _rollout_loss("f64", pop, tgt, steps, 4, rest)
+    Lo = oracle.rollout_loss(*pop.arrays(), prm, steps, tgt)
+    gp_o, gd_o, kg_o = oracle.rollout_grad(*pop.arrays(), prm, steps, tgt)
+    assert abs(L - Lo) <= 1e-12 * abs(Lo)
+    gpo = np.stack([a.cpu().numpy() for a in gp[:3]], axis=1)
+    assert np.abs(gpo - gp_o).max() <= 1e-10 * np.abs(gp_o).max()
+    assert np.abs(gp[3].cpu().numpy() - gd_o).max() <= 1e-10 * np.abs(gd_o).max()
+    np.testing.assert_allclose([gk, gg], kg_o, rtol=1e-9)
+
+
+def test_rollout_gradient_central_differences_gpu_f64():
+    """Central finite differences of the GPU FP64 rollout loss itself."""
+    prm = dict(kappa=2.0, gamma=1.0, dt=0.05, max_disp=3.0, adherence=0.0)
+    rest = dict(dt=0.05, max_disp=3.0, adherence=0.0)
+    pop = smooth_pop(300, 12.0, 90, prm, gap=1e-2, steps=5)
+    tgt = workloads.targets(pop, seed=2)
+    steps, K = 5, 2
+    L, gp, gk, gg = _rollout_loss("f64", pop, tgt, steps, K, rest)
+    ws = ms.Workspace(pop.n, dtype="f64")
+
+    def loss(arrs, kap=2.0, gam=1.0):
+        t = dev(arrs, "f64")
+        with torch.no_grad():
+            px, py, pz = msa.rollout(*t, kap, gam, ws, rest, steps, K)
+            tx, ty, tz = (torch.from_numpy(np.asarray(a)).cuda() for a in tgt)
+            return ((px - tx) ** 2 + (py - ty) ** 2 + (pz - tz) ** 2).mean().item()
+
+    h = 1e-6
+    arrs = [np.array(a) for a in pop.arrays()]
+    scale = max(float(torch.cat(gp[:3]).abs().max()), 1e-6)
+    for i in range(0, pop.n, 37):
+        for k in range(4):
+            ap = [a.copy() for a in arrs]; ap[k][i] += h
+            am = [a.copy() for a in arrs]; am[k][i] -= h
+            fd = (loss(ap) - loss(am)) / (2 * h)
+            got = gp[k][i].item()
+            ref = scale if k < 3 else max(float(gp[3].abs().max()), 1e-6)
+            assert abs(fd - got) <= 1e-6 * ref + 1e-9, (i, k, fd, got)
+    fdk = (loss(arrs, kap=2.0 + h) - loss(arrs, kap=2.0 - h)) / (2 * h)
+    fdg = (loss(arrs, gam=1.0 + h) - loss(arrs, gam=1.0 - h)) / (2 * h)
+    assert abs(fdk - gk) <= 1e-6 * abs(gk) + 1e-9
+    assert abs(fdg - gg) <= 1e-6 * abs(gg) + 1e-9

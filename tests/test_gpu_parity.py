@@ -1,0 +1,262 @@
+"""GPU parity of the plain step (grid build, 27-box gather, Eq. 1, displacement)
+against the FP64 oracle, through the C ABI.
+
+Bar: box indices, box starts, box order and neighbour sets bit-exact; forces
+and displacements within tau*S + A per agent (tau = 1e-12 on the FP64 path,
+1e-4 on the FP32 paths; S the magnitude scale of the agent's contact terms, A
+the contact-onset allowance, both from the oracle), exact zero for agents with
+no contact and no near-contact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2105_00039_amd as ms
+from paper_2105_00039_amd import workloads
+from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["f64", "f32", "f32_pos64"]
+P = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+P_FORCE = dict(kappa=2.0, gamma=1.0, dt=1.0, max_disp=1e30, adherence=0.0)   # Delta == F
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ms._lib.load()
+
+
+def _case(name):
+    r = np.random.default_rng(77)
+    if name == "lattice4096":
+        return workloads.lattice(seed=0).arrays()
+    if name == "uniform10007_n12":
+        return workloads.uniform(10007, mean_neighbors=12.0, seed=1).arrays()
+    if name == "uniform5003_n30":
+        return workloads.uniform(5003, mean_neighbors=30.0, seed=2).arrays()
+    if name == "uniform3001_n4":
+        return workloads.uniform(3001, mean_neighbors=4.0, seed=3).arrays()
+    if name == "clusters20000":
+        return workloads.clusters(20000, n_clusters=4, side=400.0, seed=4).arrays()
+    if name == "collinear999":
+        t = r.uniform(0, 2000, 999)
+        return t, np.zeros(999), np.zeros(999), r.uniform(8, 12, 999)
+    if name == "one_box777":
+        return (r.uniform(0, 6, 777), r.uniform(0, 6, 777), r.uniform(0, 6, 777), r.uniform(8, 12, 777))
+    if name == "two":
+        return np.array([0.0, 9.0]), np.zeros(2), np.zeros(2), np.array([10.0, 10.0])
+    raise KeyError(name)
+
+
+CASES = ["lattice4096", "uniform10007_n12", "uniform5003_n30", "uniform3001_n4", "clusters20000",
+         "collinear999", "one_box777", "two"]
+
+
+def dev(arrs, mode):
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(NP_IN[mode]))).cuda() for a in arrs]
+
+
+def build(arrs, mode, edge=0.0, max_boxes=None):
+    n = len(arrs[0])
+    ws = ms.Workspace(n, max_boxes=max_boxes, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t, edge=edge)
+    return ws, t
+
+
+def step(arrs, mode, params, edge=0.0):
+    ws, t = build(arrs, mode, edge)
+    D = ms.mech_step(ws, params)
+    ms.device_status(ws)
+    return ws, np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("case", CASES)
+def test_grid_bit_exact(case, mode):
+    arrs = _case(case)
+    ws, _ = build(arrs, mode)
+    ms.device_status(ws)
+    g = ms.grid_get(ws)
+    o = oracle_inputs(arrs, mode)
+    origin, edge, dims, nb = oracle.geometry(*o)
+    box, start, perm = oracle.grid(*o)
+    info = g["info"][0]
+    assert info["edge"] == edge
+    assert tuple(info["dims"]) == tuple(int(v) for v in dims)
+    assert np.array_equal(np.array(info["origin"]), origin)
+    assert info["n_boxes"] == nb
+    assert np.array_equal(g["box_id"].cpu().numpy(), box)
+    assert np.array_equal(g["start"].cpu().numpy(), start)
+    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("case", CASES)
+def test_neighbors_bit_exact(case, mode):
+    arrs = _case(case)
+    ws, _ = build(arrs, mode)
+    c, off, lst = ms.neighbors(ws)
+    oc, ooff, olst = oracle.neighbors(*oracle_inputs(arrs, mode))
+    assert np.array_equal(c.cpu().numpy(), oc)
+    assert np.array_equal(off.cpu().numpy(), ooff)
+    assert np.array_equal(lst.cpu().numpy(), olst)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("case", CASES)
+def test_force_and_displacement_parity(case, mode):
+    arrs = _case(case)
+    o = oracle_inputs(arrs, mode)
+    S, A, C = oracle.tolerance_scales(*o, 2.0, 1.0, UNIT[mode])
+    # forces: with dt = 1 and no bound the displacement is the force itself
+    _, F = step(arrs, mode, P_FORCE)
+    Fo, _ = oracle.step(*o, P_FORCE)
+    check_vectors(F, Fo, force_bound(S, A, mode), f"force {case} {mode}")
+    # displacements with the benchmark parameters
+    _, D = step(arrs, mode, P)
+    _, Do = oracle.step(*o, P)
+    bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+    check_vectors(D, Do, bound, f"displacement {case} {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_clamp_and_adherence(mode):
+    arrs = _case("uniform5003_n30")
+    o = oracle_inputs(arrs, mode)
+    S, A, _ = oracle.tolerance_scales(*o, 2.0, 1.0, UNIT[mode])
+    prm = dict(kappa=2.0, gamma=1.0, dt=1.0, max_disp=0.3, adherence=0.0)
+    _, D = step(arrs, mode, prm)
+    Fo, Do = oracle.step(*o, prm)
+    nF = np.linalg.norm(Fo, axis=1)
+    assert np.sum(nF > 0.3) > 100 and np.sum((nF < 0.3) & (nF > 0)) > 100
+    bound = prm["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+    check_vectors(D, Do, bound, f"clamped displacement {mode}")
+    assert np.all(np.linalg.norm(D, axis=1) <= 0.3 * (1 + 8 * UNIT[mode]))
+    # adherence: agents clearly below the threshold stay, clearly above move
+    a = float(np.median(nF[nF > 0]))
+    prm = dict(P, adherence=a)
+    _, D = step(arrs, mode, prm)
+    _, Do = oracle.step(*o, prm)
+    clear = np.abs(nF - a) > 1e-3 * a + force_bound(S, A, mode)
+    bound = prm["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+    check_vectors(D[clear], Do[clear], bound[clear], f"adherence {mode}")
+    assert np.all(D[clear & (nF <= a)] == 0)
+    # max_disp = 0 freezes every agent
+    _, D = step(arrs, mode, dict(P, max_disp=0.0))
+    assert np.all(D == 0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_repeat_is_bitwise_identical(mode):
+    arrs = _case("clusters20000")
+    ws, t = build(arrs, mode)
+    D1 = [a.clone() for a in ms.mech_step(ws, P)]
+    ms.grid_build(ws, *t)
+    D2 = ms.mech_step(ws, P)
+    for a, b in zip(D1, D2):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_integrate_exact(mode):
+    arrs = _case("uniform10007_n12")
+    ws, t = build(arrs, mode)
+    D = ms.mech_step(ws, P)
+    x0 = [a.cpu().numpy().copy() for a in t[:3]]
+    ms.integrate(*t[:3], *D)
+    for k in range(3):
+        want = x0[k] + D[k].cpu().numpy().astype(x0[k].dtype)
+        assert np.array_equal(t[k].cpu().numpy(), want)
+
+
+def test_edge_cases_and_errors():
+    # n = 0
+    ws = ms.Workspace(16, dtype="f32")
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    ms.grid_build(ws, e, e, e, e)
+    D = ms.mech_step(ws, P)
+    assert all(a.numel() == 0 for a in D)
+    # n = 1
+    arrs = (np.array([3.0]), np.array([4.0]), np.array([5.0]), np.array([10.0]))
+    _, D1 = step(arrs, "f64", P)
+    assert np.all(D1 == 0)
+    # device-detected errors, then a good build on the same workspace
+    base = [np.array([0.0, 9.0, 20.0]), np.zeros(3), np.zeros(3), np.array([10.0, 10.0, 10.0])]
+    for mode in MODES:
+        ws = ms.Workspace(3, dtype=mode)
+        bad = [a.copy() for a in base]
+        bad[0][1] = np.nan
+        ms.grid_build(ws, *dev(bad, mode))
+        with pytest.raises(ms.MechStepError) as ei:
+            ms.device_status(ws)
+        assert ei.value.status == ms._lib.MS_EINPUT
+        bad = [a.copy() for a in base]
+        bad[3][2] = -1.0
+        ms.grid_build(ws, *dev(bad, mode))
+        with pytest.raises(ms.MechStepError) as ei:
+            ms.device_status(ws)
+        assert ei.value.status == ms._lib.MS_EINPUT
+        ms.grid_build(ws, *dev(base, mode), edge=5.0)
+        with pytest.raises(ms.MechStepError) as ei:
+            ms.device_status(ws)
+        assert ei.value.status == ms._lib.MS_EINVAL
+        t = dev(base, mode)
+        ms.grid_build(ws, *t)
+        ms.device_status(ws)
+        D = ms.mech_step(ws, P)
+        Fo, Do = oracle.step(*oracle_inputs(base, mode), P)
+        assert np.allclose(D[0].cpu().numpy(), Do[:, 0], rtol=1e-5, atol=0)
+    # capacity: far-apart agents need more boxes than the workspace holds
+    far = [np.array([0.0, 1e4]), np.zeros(2), np.zeros(2), np.array([10.0, 10.0])]
+    ws = ms.Workspace(2, max_boxes=64, dtype="f64")
+    ms.grid_build(ws, *dev(far, "f64"))
+    with pytest.raises(ms.MechStepError) as ei:
+        ms.device_status(ws)
+    assert ei.value.status == ms._lib.MS_ECAPACITY
+    # host-side errors
+    ws = ms.Workspace(4, dtype="f32")
+    x = torch.zeros(8, dtype=torch.float32, device="cuda")
+    with pytest.raises(ms.MechStepError) as ei:
+        ms.grid_build(ws, x, x, x, x)
+    assert ei.value.status == ms._lib.MS_ECAPACITY
+    with pytest.raises(TypeError):
+        ms.grid_build(ws, x.double(), x.double(), x.double(), x.double())
+    ms.grid_build(ws, x[:4], x[:4], x[:4], x[:4] + 1)
+    with pytest.raises(ms.MechStepError) as ei:
+        ms.mech_step(ws, dict(P, dt=-1.0))
+    assert ei.value.status == ms._lib.MS_EINVAL
+    # a larger edge than the largest diameter gives the same forces
+    arrs = _case("uniform3001_n4")
+    _, Da = step(arrs, "f64", P)
+    _, Db = step(arrs, "f64", P, edge=30.0)
+    S, A, _ = oracle.tolerance_scales(*arrs, 2.0, 1.0, UNIT["f64"])
+    check_vectors(Da, Db, 2 * P["dt"] * force_bound(S, A, "f64"), "edge 30")
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_full_size_uniform_2M(mode):
+    """Benchmark size (2,097,152 agents, ~12 neighbours) in the benchmark's
+    launch configuration: grid bit-exact, every agent's displacement within
+    tolerance."""
+    pop = workloads.uniform(workloads.FULL_N, mean_neighbors=12.0, seed=0)
+    arrs = pop.arrays()
+    ws, t = build(arrs, mode)
+    D = ms.mech_step(ws, P)
+    ms.device_status(ws)
+    g = ms.grid_get(ws)
+    o = oracle_inputs(arrs, mode)
+    box, start, perm = oracle.grid(*o)
+    assert np.array_equal(g["box_id"].cpu().numpy(), box)
+    assert np.array_equal(g["start"].cpu().numpy(), start)
+    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
+    _, Do = oracle.step(*o, P)
+    S, A, C = oracle.tolerance_scales(*o, 2.0, 1.0, UNIT[mode])
+    bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+    worst = check_vectors(Dg, Do, bound, f"2M {mode}")
+    print(f"2M {mode}: worst err/bound {worst:.3f}, mean contacts {C.mean():.2f}")
