@@ -10,9 +10,9 @@ NP_IN = {"f32": np.float32, "f64": np.float64, "f32_pos64": np.float64}
 
 def oracle_inputs(pop_arrays, mode):
     """What the oracle is fed for a precision mode: the exact values the GPU
-    path computes with, widened to FP64 (FP32 inputs widen exactly; the mixed
-    mode rounds its FP64 master positions to FP32 first)."""
-    if mode == "f32_pos64":
+    path computes with, widened to FP64: both FP32 modes see the inputs rounded
+    to nearest FP32 (the mixed mode rounds its FP64 master positions)."""
+    if mode in ("f32", "f32_pos64"):
         return tuple(np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
                      for a in pop_arrays)
     return tuple(np.asarray(a).astype(np.float64) for a in pop_arrays)
