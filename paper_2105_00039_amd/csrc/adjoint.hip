@@ -44,8 +44,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
+    __shared__ int32_t lst[kMaxContacts * kBlock];
     if (hdr->error) return;
-    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
     if (BATCHED) s = block_sim(off, B, n, k0, k);
@@ -55,7 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, fx, fy, fz);
+    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                         fx, fy, fz);
     const int32_t o = perm[k];
     const Real gx = gdx[o], gy = gdy[o], gz = gdz[o];
     const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
@@ -116,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
     if (hdr->error) return;
-    const int64_t k0 = (int64_t)blockIdx.x * kBlock;
+    const unsigned vb = xcd_block();   // partials are indexed by this virtual block
+    const int64_t k0 = (int64_t)vb * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
     if (BATCHED) {
@@ -182,8 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const double tk = block_sum_fixed(kb, s_w);
         const double tg = block_sum_fixed(gb, s_w);
         if (threadIdx.x == 0) {
-            partials[2 * blockIdx.x] = tk;
-            partials[2 * blockIdx.x + 1] = tg;
+            partials[2 * vb] = tk;
+            partials[2 * vb + 1] = tg;
         }
     } else {
         const int slo = s_rng[0], shi = s_rng[1];
@@ -192,8 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             const double tk = block_sum_fixed(mine ? kb : 0.0, s_w);
             const double tg = block_sum_fixed(mine ? gb : 0.0, s_w);
             if (threadIdx.x == 0) {
-                partials[2 * ((int64_t)blockIdx.x + t)] = tk;
-                partials[2 * ((int64_t)blockIdx.x + t) + 1] = tg;
+                partials[2 * ((int64_t)vb + t)] = tk;
+                partials[2 * ((int64_t)vb + t) + 1] = tg;
             }
         }
     }

@@ -11,9 +11,14 @@ namespace ms {
 
 constexpr int kBlock = 256;           // threads per block for every per-agent kernel
 constexpr int kWave = 64;             // CDNA wavefront
-constexpr int kScanItems = 8;         // items per thread in the box scan
+constexpr int kScanItems = 8;         // items per thread in the neighbour-offset scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBoundsChunk = kBlock * 16;   // agents per block in the bounds pass
+constexpr int kTileA = kBlock * 16;   // agents per block in the bucket histogram/partition
+constexpr int kBucketsMax = 4096;     // bucket count limit of the two-level sort
+constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in [6, 13]
+constexpr int kSBMax = 13;
+constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 
 // Device error bits (ms_grid_info.error and the workspace error word).
 enum : uint32_t {
@@ -21,18 +26,20 @@ enum : uint32_t {
     ERR_NEGDIAM = 2u,     // negative diameter
     ERR_EDGE = 4u,        // edge <= 0, non-finite, or below the largest diameter
     ERR_CAPACITY = 8u,    // more boxes than the workspace holds (or int32 overflow)
+    ERR_OFFSETS = 16u,    // simulation offsets do not partition [0, n)
 };
 
 // Workspace header (first 256 bytes of the device buffer).
 struct Header {
     uint32_t error;        // error bits of the last build, rewritten by every build
-    uint32_t epoch;        // build counter (1 .. 2^30-1), tags the scan tile flags
-    uint32_t scan_ticket;  // dynamic tile index of the look-back scan
     uint32_t n_sims;
+    int32_t sb;            // bucket shift of the last build
+    int32_t nb;            // bucket count of the last build
     int64_t total_boxes;   // boxes over all simulations of the last build
     int64_t n_agents;
     int64_t need_boxes;    // boxes the last build asked for (even when over capacity)
-    uint8_t pad[256 - 40];
+    uint32_t off_err;      // simulation-offset check of the current build (cleared after use)
+    uint8_t pad[256 - 44];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -48,15 +55,15 @@ struct SimGeom {
 };
 static_assert(sizeof(SimGeom) == 64, "geom size");
 
-// Per-simulation bounds accumulators: order-preserving integer encodings of
-// min x,y,z, max x,y,z, max d, and an error-flag word.
-struct SimAcc {
-    unsigned long long lo[3];
-    unsigned long long hi[3];
-    unsigned long long dmax;
-    unsigned long long flags;
+// Per-(block, simulation) bounds partial: min x,y,z, max x,y,z, max d, flags.
+struct BoundsPart {
+    double lo[3];
+    double hi[3];
+    double dmax;
+    uint32_t flags;
+    uint32_t pad;
 };
-static_assert(sizeof(SimAcc) == 64, "acc size");
+static_assert(sizeof(BoundsPart) == 64, "bounds partial size");
 
 struct alignas(16) F4 { float x, y, z, w; };
 struct alignas(32) D4 { double x, y, z, w; };
@@ -68,9 +75,9 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
-    size_t hdr, acc, geom, off, box_id, slot, count, start, flags, perm_tmp, perm, payload, fbar,
-        partials, scratch64, total;
-    int64_t max_agents, max_boxes, n_scan_tiles, n_part;
+    size_t hdr, geom, off, bpart, box_id, start, hist, bstart, key2, idx2, pay2, tmp, perm,
+        payload, fbar, partials, scratch64, total;
+    int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
 };
@@ -84,31 +91,34 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     L.max_boxes = max_boxes;
     L.max_sims = max_sims;
     L.dtype = dtype;
-    const size_t real = (dtype == MS_F64) ? 8 : 4;
     const size_t pay = (dtype == MS_F64) ? sizeof(D4) : sizeof(F4);
     const int64_t na = max_agents > 0 ? max_agents : 1;
     const int64_t nblk = (na + kBlock - 1) / kBlock;
-    L.n_scan_tiles = (max_boxes + 1 + kScanTile - 1) / kScanTile;
+    L.nblk_a_max = (na + kTileA - 1) / kTileA;
+    L.nblk_b_max = (na + kBoundsChunk - 1) / kBoundsChunk;
+    int64_t nbc = (max_boxes + (1 << kSBMin) - 1) >> kSBMin;
+    L.nb_cap = nbc < kBucketsMax ? (nbc > 0 ? nbc : 1) : kBucketsMax;
     L.n_part = nblk + max_sims + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
     L.hdr = take(sizeof(Header));
-    L.acc = take(sizeof(SimAcc) * (size_t)max_sims);
     L.geom = take(sizeof(SimGeom) * (size_t)max_sims);
     L.off = take(8 * (size_t)(max_sims + 1));
+    L.bpart = take(sizeof(BoundsPart) * (size_t)(L.nblk_b_max + max_sims + 1));
     L.box_id = take(4 * (size_t)na);
-    L.slot = take(4 * (size_t)na);
-    L.count = take(4 * (size_t)(max_boxes + 1));
     L.start = take(4 * (size_t)(max_boxes + 2));
-    L.flags = take(8 * (size_t)L.n_scan_tiles);
-    L.perm_tmp = take(4 * (size_t)na);
+    L.hist = take(4 * (size_t)(L.nb_cap * L.nblk_a_max));
+    L.bstart = take(4 * (size_t)(2 * L.nb_cap + 2));
+    L.key2 = take(4 * (size_t)na);
+    L.idx2 = take(4 * (size_t)na);
+    L.pay2 = take(pay * (size_t)na);
+    L.tmp = take(4 * (size_t)na);
     L.perm = take(4 * (size_t)na);
     L.payload = take(pay * (size_t)na);
     L.fbar = take(pay * (size_t)na);
     L.partials = take(16 * (size_t)L.n_part);
     // int64 scratch for the neighbour-offset scan: one entry per scan tile of n+1 items
     L.scratch64 = take(8 * (size_t)((na + 1 + kScanTile - 1) / kScanTile + 1));
-    (void)real;
     L.total = o;
     return L;
 }
@@ -116,15 +126,17 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
 // Device pointers of every region.
 struct Dev {
     Header* hdr;
-    SimAcc* acc;
     SimGeom* geom;
     int64_t* off;
+    BoundsPart* bpart;
     int32_t* box_id;
-    int32_t* slot;
-    int32_t* count;
     int32_t* start;
-    unsigned long long* flags;
-    int32_t* perm_tmp;
+    int32_t* hist;      // [bucket][block-A] histogram, scanned in place along each row
+    int32_t* bstart;    // [0, nb]: bucket starts; [nb_cap+1 ...]: bucket totals
+    int32_t* key2;
+    int32_t* idx2;
+    void* pay2;
+    int32_t* tmp;
     int32_t* perm;
     void* payload;
     void* fbar;
@@ -137,15 +149,17 @@ inline Dev resolve(const Layout& L, void* base)
     char* b = static_cast<char*>(base);
     Dev d;
     d.hdr = reinterpret_cast<Header*>(b + L.hdr);
-    d.acc = reinterpret_cast<SimAcc*>(b + L.acc);
     d.geom = reinterpret_cast<SimGeom*>(b + L.geom);
     d.off = reinterpret_cast<int64_t*>(b + L.off);
+    d.bpart = reinterpret_cast<BoundsPart*>(b + L.bpart);
     d.box_id = reinterpret_cast<int32_t*>(b + L.box_id);
-    d.slot = reinterpret_cast<int32_t*>(b + L.slot);
-    d.count = reinterpret_cast<int32_t*>(b + L.count);
     d.start = reinterpret_cast<int32_t*>(b + L.start);
-    d.flags = reinterpret_cast<unsigned long long*>(b + L.flags);
-    d.perm_tmp = reinterpret_cast<int32_t*>(b + L.perm_tmp);
+    d.hist = reinterpret_cast<int32_t*>(b + L.hist);
+    d.bstart = reinterpret_cast<int32_t*>(b + L.bstart);
+    d.key2 = reinterpret_cast<int32_t*>(b + L.key2);
+    d.idx2 = reinterpret_cast<int32_t*>(b + L.idx2);
+    d.pay2 = b + L.pay2;
+    d.tmp = reinterpret_cast<int32_t*>(b + L.tmp);
     d.perm = reinterpret_cast<int32_t*>(b + L.perm);
     d.payload = b + L.payload;
     d.fbar = b + L.fbar;

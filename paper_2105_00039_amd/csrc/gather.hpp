@@ -69,36 +69,98 @@ __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int
     }
 }
 
-// Eq. 1 summed over every candidate in contact with agent `pi`.
-// Contact: |u|^2 < (ri + rj)^2, |u| > 0 and delta = ri + rj - |u| > 0.
+// Virtual block index that gives each XCD a contiguous share of the sorted
+// agents.  Work-groups are dispatched round-robin over the 8 XCDs, so block b
+// runs on XCD b % 8; mapping those blocks to one contiguous range keeps the
+// candidate rows a block reads in the L2 of the XCD that reads them.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+constexpr int kMaxContacts = 16;   // per-lane contact list length in LDS
+
+// Force of one contact (Eq. 1) added to a; nothing if the pair does not
+// overlap.  FP32: 1/l from rsq, rho from a reciprocal.
+__device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float kap, float gam,
+                                              float& ax, float& ay, float& az)
+{
+    const float ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+    const float l2 = ux * ux + uy * uy + uz * uz;
+    const float rs = pi.w + q.w;
+    const float il = __builtin_amdgcn_rsqf(l2);
+    const float delta = rs - l2 * il;
+    if (delta > 0.0f) {
+        const float rho = pi.w * q.w * __builtin_amdgcn_rcpf(rs);
+        const float sv = kap * delta - gam * __builtin_amdgcn_sqrtf(rho * delta);
+        const float sl = sv * il;
+        ax += sl * ux;
+        ay += sl * uy;
+        az += sl * uz;
+    }
+}
+
+__device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double kap, double gam,
+                                              double& ax, double& ay, double& az)
+{
+    const double ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+    const double l2 = ux * ux + uy * uy + uz * uz;
+    const double rs = pi.w + q.w;
+    const double l = sqrt(l2);
+    const double delta = rs - l;
+    if (delta > 0.0) {
+        const double rho = pi.w * q.w / rs;
+        const double sv = kap * delta - gam * sqrt(rho * delta);
+        const double sl = sv / l;
+        ax += sl * ux;
+        ay += sl * uy;
+        az += sl * uz;
+    }
+}
+
+// Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
+// order.  Two phases keep the wavefront busy: the cheap candidate test
+// (|u|^2 < (ri + rj)^2, |u| > 0) appends candidate indices to this lane's
+// list in LDS (`lst`, stride kBlock); the contact math then runs over the
+// list.  A full list is drained before the scan continues, so the order of
+// the sum is the candidate order either way.
 template <typename Real, typename Pay>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           const int32_t* __restrict__ start,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          Real& fx, Real& fy, Real& fz)
+                                          int32_t* lst, Real& fx, Real& fy, Real& fz)
 {
-    fx = fy = fz = (Real)0;
     Real ax = 0, ay = 0, az = 0;
-    for_each_run(g, c, start, [&](int j0, int j1) {
-        for (int j = j0; j < j1; ++j) {
-            const Pay q = pay[j];
-            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-            const Real l2 = ux * ux + uy * uy + uz * uz;
-            const Real rs = pi.w + q.w;
-            if (l2 < rs * rs && l2 > (Real)0) {
-                const Real l = fsqrt(l2);
-                const Real delta = rs - l;
-                if (delta > (Real)0) {
-                    const Real rho = pi.w * q.w * frcp(rs);
-                    const Real s = kap * delta - gam * fsqrt(rho * delta);
-                    const Real sl = s * frcp(l);
-                    ax += sl * ux;
-                    ay += sl * uy;
-                    az += sl * uz;
-                }
-            }
+    int cnt = 0;
+    auto drain = [&]() {
+        for (int t = 0; t < cnt; ++t) {
+            const Pay q = pay[lst[t * kBlock]];
+            contact_force(pi, q, kap, gam, ax, ay, az);
         }
+        cnt = 0;
+    };
+    auto test = [&](const Pay& q, int j) {
+        const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+        const Real l2 = ux * ux + uy * uy + uz * uz;
+        const Real rs = pi.w + q.w;
+        if (l2 < rs * rs && l2 > (Real)0) {
+            lst[cnt * kBlock] = j;
+            if (++cnt == kMaxContacts) drain();
+        }
+    };
+    for_each_run(g, c, start, [&](int j0, int j1) {
+        int j = j0;
+        for (; j + 1 < j1; j += 2) {
+            const Pay q0 = pay[j];
+            const Pay q1 = pay[j + 1];
+            test(q0, j);
+            test(q1, j + 1);
+        }
+        if (j < j1) test(pay[j], j);
     });
+    drain();
     fx = ax; fy = ay; fz = az;
 }
 
