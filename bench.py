@@ -227,14 +227,39 @@ def cpu_baseline(arrs, budget_s=12.0, max_steps=3):
                        f"population, FP64, single thread, {sec:.1f} s")
 
 
-def traffic_from_profiles(kernel="k_force", workload="uniform2M_n12_f32"):
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+FORCE_SOURCES = ("paper_2105_00039_amd/csrc/force.hip", "paper_2105_00039_amd/csrc/gather.hpp",
+                 "paper_2105_00039_amd/csrc/common.hpp")
+
+
+def force_source_hash():
+    """Hash of the force kernel's sources: a traffic figure measured on other
+    sources is stale and reported as null."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FORCE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per force launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe), if it was taken on the
+    current force sources."""
+    path = os.path.join(ROOT, "profiles", f"k_force_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("force_source_hash") != force_source_hash():
+        return None
     try:
-        with open(path) as f:
-            return json.load(f).get("hbm_bytes_per_launch")
-    except (OSError, ValueError):
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
 
 
@@ -250,6 +275,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the eager K-step pass (for rocprofv3 runs)")
+    ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
+                    help="with --profile-only: also run the copy probe once on MIB MiB "
+                         "(the known-size kernel that scales rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -274,6 +302,14 @@ def main():
     if args.profile_only:
         sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
         log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
+        if args.probe_copy:
+            nbytes = args.probe_copy << 20
+            src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            ms.copy_probe(dst, src)
+            torch.cuda.synchronize()
+            log(f"copy probe: {nbytes} bytes read, {nbytes} bytes written; force sources "
+                f"{force_source_hash()}")
         return
 
     # headline: graph-replayed steps
@@ -294,7 +330,7 @@ def main():
     achieved = flops / (force_ms * 1e-3)
     fb = force_bytes(N, st["n_boxes"], S)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                    frac=achieved / peak, traffic=traffic_from_profiles(workload=f"{name}_{args.dtype}"),
+                    frac=achieved / peak, traffic=traffic_from_profiles(f"{name}_{args.dtype}"),
                     kernel="k_force", flops_per_agent=flops_agent, force_us=force_ms * 1e3,
                     force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9)
     balg = bytes_alg(N, st["n_boxes"], S)

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    __shared__ int32_t lst[kMaxContacts * kBlock];
+    __shared__ uint32_t lst[kMaxContacts * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;

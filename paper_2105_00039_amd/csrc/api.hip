@@ -97,6 +97,10 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
         return fail(MS_ECAPACITY, "ms_workspace_init: max_boxes must be in [1, 2^31-1)");
     if (max_sims < 1 || max_sims > (1 << 24))
         return fail(MS_ECAPACITY, "ms_workspace_init: max_sims must be in [1, 2^24]");
+    const uint64_t pay_bytes = (uint64_t)max_agents * (dtype == MS_F64 ? 32u : 16u);
+    if (pay_bytes >= (1ull << 32))
+        return fail(MS_ECAPACITY, "ms_workspace_init: max_agents too large for this dtype "
+                                  "(sorted payload must stay below 4 GiB)");
     const ms::Layout L = ms::make_layout(max_agents, max_boxes, max_sims, dtype);
     if (bytes < L.total)
         return fail(MS_EINVAL, "ms_workspace_init: %zu bytes given, %zu needed", bytes, L.total);

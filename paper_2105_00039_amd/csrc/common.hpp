@@ -39,7 +39,8 @@ struct Header {
     int64_t n_agents;
     int64_t need_boxes;    // boxes the last build asked for (even when over capacity)
     uint32_t off_err;      // simulation-offset check of the current build (cleared after use)
-    uint8_t pad[256 - 44];
+    int32_t total_rows;    // x-rows of boxes over all simulations of the last build
+    uint8_t pad[256 - 48];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -50,7 +51,7 @@ struct SimGeom {
     int32_t dims[3];
     int32_t error;
     int32_t box_base;
-    int32_t pad;
+    int32_t row_base;   // first global x-row (dims[1]*dims[2] rows per simulation)
     int64_t n_boxes;
 };
 static_assert(sizeof(SimGeom) == 64, "geom size");

@@ -80,10 +80,11 @@ __device__ __forceinline__ unsigned xcd_block()
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-constexpr int kMaxContacts = 16;   // per-lane contact list length in LDS
+constexpr int kMaxContacts = 20;   // per-lane contact list length in LDS
 
-// Force of one contact (Eq. 1) added to a; nothing if the pair does not
-// overlap.  FP32: 1/l from rsq, rho from a reciprocal.
+// Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
+// overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
+// a reciprocal.
 __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float kap, float gam,
                                               float& ax, float& ay, float& az)
 {
@@ -92,7 +93,7 @@ __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float k
     const float rs = pi.w + q.w;
     const float il = __builtin_amdgcn_rsqf(l2);
     const float delta = rs - l2 * il;
-    if (delta > 0.0f) {
+    if (delta > 0.0f && l2 > 0.0f) {
         const float rho = pi.w * q.w * __builtin_amdgcn_rcpf(rs);
         const float sv = kap * delta - gam * __builtin_amdgcn_sqrtf(rho * delta);
         const float sl = sv * il;
@@ -110,7 +111,7 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
     const double rs = pi.w + q.w;
     const double l = sqrt(l2);
     const double delta = rs - l;
-    if (delta > 0.0) {
+    if (delta > 0.0 && l2 > 0.0) {
         const double rho = pi.w * q.w / rs;
         const double sv = kap * delta - gam * sqrt(rho * delta);
         const double sl = sv / l;
@@ -120,46 +121,103 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
     }
 }
 
+// The 9 runs of the stencil for the force sums, all bounds loaded up front
+// (one memory round trip), trimmed to the boxes the agent can touch: a
+// partner is at most e/2 in radius (the edge is at least the largest
+// diameter), so a contact lies within reach = r_i + e/2 of the centre.  A
+// (dy, dz) row whose y-z distance from the agent is >= reach is skipped, and
+// the first / last box of a run is dropped when its x distance (combined
+// with the row's y-z distance) is >= reach.  Distances are the agent's
+// offsets from its own box faces, in FP64, with a relative margin of 1e-9 on
+// reach, so no box holding a contact is ever dropped.  Out-of-range rows give
+// empty runs.
+struct Runs { int b[9], e[9]; };
+
+template <typename Real>
+__device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
+                                             const int32_t* __restrict__ start, Real px, Real py,
+                                             Real pz, Real ri)
+{
+    const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
+    const double e = g.edge;
+    const double reach = ((double)ri + 0.5 * e) * (1.0 + 1e-9);
+    const double r2 = reach * reach;
+    // offsets of the agent from the lower (lo) and upper (hi) faces of its box
+    const double lx = ((double)px - g.origin[0]) - c.ix * e, hx = e - lx;
+    const double ly = ((double)py - g.origin[1]) - c.iy * e, hy = e - ly;
+    const double lz = ((double)pz - g.origin[2]) - c.iz * e, hz = e - lz;
+    const double dy2[3] = {ly * ly, 0.0, hy * hy};
+    const double dz2[3] = {lz * lz, 0.0, hz * hz};
+    Runs R;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int cz = c.iz + r / 3 - 1, cy = c.iy + r % 3 - 1;
+        const double yz = dz2[r / 3] + dy2[r % 3];
+        const bool ok = cz >= 0 && cz < nz && cy >= 0 && cy < ny && yz < r2;
+        const int x0 = (c.ix > 0 && lx * lx + yz < r2) ? c.ix - 1 : c.ix;
+        const int x1 = (c.ix + 1 < nx && hx * hx + yz < r2) ? c.ix + 1 : c.ix;
+        const int row = g.box_base + (cz * ny + cy) * nx;
+        const int i0 = ok ? row + x0 : 0, i1 = ok ? row + x1 + 1 : 0;
+        R.b[r] = start[i0];
+        R.e[r] = ok ? start[i1] : R.b[r];
+    }
+    return R;
+}
+
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
-// order.  Two phases keep the wavefront busy: the cheap candidate test
-// (|u|^2 < (ri + rj)^2, |u| > 0) appends candidate indices to this lane's
-// list in LDS (`lst`, stride kBlock); the contact math then runs over the
-// list.  A full list is drained before the scan continues, so the order of
-// the sum is the candidate order either way.
+// order.  Two phases keep the wavefront busy.  The scan tests each candidate
+// with |u|^2 < (ri + rj)^2 only and appends its byte offset to this lane's
+// list in LDS (`lst`, stride kBlock) without branching: the slot is always
+// written and the cursor advances on a hit.  Four candidates are loaded
+// before any is tested (indices clamped into the run, surplus tests masked)
+// so four loads are in flight per lane.  The contact math then runs over the
+// list; it also drops the agent itself (|u| = 0).  A full list is drained
+// before the scan continues, so the sum follows the candidate order.
+// Offsets are 32-bit, so a workspace holds fewer than 2^32 payload bytes.
 template <typename Real, typename Pay>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           const int32_t* __restrict__ start,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          int32_t* lst, Real& fx, Real& fy, Real& fz)
+                                          uint32_t* lst, Real& fx, Real& fy, Real& fz)
 {
+    constexpr uint32_t P = (uint32_t)sizeof(Pay);
+    const char* base = reinterpret_cast<const char*>(pay);
     Real ax = 0, ay = 0, az = 0;
     int cnt = 0;
     auto drain = [&]() {
         for (int t = 0; t < cnt; ++t) {
-            const Pay q = pay[lst[t * kBlock]];
+            const Pay q = *reinterpret_cast<const Pay*>(base + lst[t * kBlock]);
             contact_force(pi, q, kap, gam, ax, ay, az);
         }
         cnt = 0;
     };
-    auto test = [&](const Pay& q, int j) {
+    auto test = [&](const Pay& q, uint32_t off, bool live) {
         const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
         const Real l2 = ux * ux + uy * uy + uz * uz;
         const Real rs = pi.w + q.w;
-        if (l2 < rs * rs && l2 > (Real)0) {
-            lst[cnt * kBlock] = j;
-            if (++cnt == kMaxContacts) drain();
-        }
+        lst[cnt * kBlock] = off;
+        cnt += (live && l2 < rs * rs) ? 1 : 0;
+        if (cnt == kMaxContacts) drain();
     };
-    for_each_run(g, c, start, [&](int j0, int j1) {
-        int j = j0;
-        for (; j + 1 < j1; j += 2) {
-            const Pay q0 = pay[j];
-            const Pay q1 = pay[j + 1];
-            test(q0, j);
-            test(q1, j + 1);
+    const Runs R = stencil_runs<Real>(g, c, start, pi.x, pi.y, pi.z, pi.w);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const uint32_t end = (uint32_t)R.e[r] * P;
+        const uint32_t last = end - P;
+        for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
+            const uint32_t o1 = off + P < end ? off + P : last;
+            const uint32_t o2 = off + 2 * P < end ? off + 2 * P : last;
+            const uint32_t o3 = off + 3 * P < end ? off + 3 * P : last;
+            const Pay q0 = *reinterpret_cast<const Pay*>(base + off);
+            const Pay q1 = *reinterpret_cast<const Pay*>(base + o1);
+            const Pay q2 = *reinterpret_cast<const Pay*>(base + o2);
+            const Pay q3 = *reinterpret_cast<const Pay*>(base + o3);
+            test(q0, off, true);
+            test(q1, o1, off + P < end);
+            test(q2, o2, off + 2 * P < end);
+            test(q3, o3, off + 3 * P < end);
         }
-        if (j < j1) test(pay[j], j);
-    });
+    }
     drain();
     fx = ax; fy = ay; fz = az;
 }

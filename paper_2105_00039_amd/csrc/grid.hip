@@ -242,21 +242,25 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
     __shared__ uint32_t s_err;
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
-    long long running = 0;
+    long long running = 0, rows = 0;
     for (int c = 0; c < B; c += 1024) {
         const int s = c + threadIdx.x;
-        long long nb = 0;
+        long long nb = 0, nr = 0;
         if (s < B) {
             nb = geom[s].n_boxes;
+            nr = nb > 0 ? (long long)geom[s].dims[1] * geom[s].dims[2] : 0;
             if (geom[s].error) atomicOr(&s_err, (uint32_t)geom[s].error);
         }
-        long long tot;
+        long long tot, rtot;
         const long long base = block_excl_scan<1024, long long>(nb, s_wave, tot);
+        const long long rbase = block_excl_scan<1024, long long>(nr, s_wave, rtot);
         if (s < B) {
             const long long gb = running + base;
             geom[s].box_base = gb < 2147483647ll ? (int32_t)gb : 0;
+            geom[s].row_base = (int32_t)(rows + rbase);
         }
         running += tot;
+        rows += rtot;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -274,6 +278,7 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         hdr->n_sims = (uint32_t)B;
         hdr->sb = sb;
         hdr->nb = err ? 0 : (int32_t)nbk;
+        hdr->total_rows = err ? 0 : (int32_t)rows;
         if (!err) start[running] = (int32_t)n;
     }
 }
@@ -373,6 +378,9 @@ __global__ __launch_bounds__(1024) void k_bucketscan(const Header* __restrict__ 
 
 // ---------------------------------------------------------------- partition
 
+// Each block orders its tile by bucket in LDS, then writes every bucket's run
+// contiguously (consecutive lanes -> consecutive addresses), reading the
+// agents' inputs inside the tile.
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In* __restrict__ x,
                                                       const typename Mode<M>::In* __restrict__ y,
@@ -387,31 +395,84 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
                                                       typename Mode<M>::Pay* __restrict__ pay2)
 {
     using Real = typename Mode<M>::Real;
-    __shared__ int32_t cur[kBucketsMax];
+    constexpr int IT = kTileA / kBlock;
+    __shared__ int32_t cnt[kBucketsMax];     // tile counts, then tile-local bucket starts
+    __shared__ int32_t gcur[kBucketsMax];    // global start of this tile's run per bucket
+    __shared__ uint16_t order[kTileA];       // tile-local index in bucket order
+    __shared__ int32_t s_wave[kBlock / kWave];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
-    for (int b = threadIdx.x; b < nbk; b += kBlock)
-        cur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + blockIdx.x];
+    for (int b = threadIdx.x; b < nbk; b += kBlock) cnt[b] = 0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kTileA;
-    const int64_t c1 = (c0 + kTileA < n) ? c0 + kTileA : n;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-        const int key = box_id[i];
-        const int pos = atomicAdd(&cur[key >> sb], 1);
-        key2[pos] = key;
-        idx2[pos] = (int32_t)i;
-        typename Mode<M>::Pay q;
-        q.x = (Real)x[i];
-        q.y = (Real)y[i];
-        q.z = (Real)z[i];
-        q.w = (Real)0.5 * (Real)d[i];
-        pay2[pos] = q;
+    const int tn = (int)((c0 + kTileA < n) ? kTileA : n - c0);
+    int bk[IT], rk[IT];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        bk[t] = -1;
+        if (e < tn) {
+            bk[t] = box_id[c0 + e] >> sb;
+            rk[t] = atomicAdd(&cnt[bk[t]], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the tile counts over buckets; global run starts
+    const int per = (nbk + kBlock - 1) / kBlock;
+    const int b0 = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int b = b0; b < b0 + per && b < nbk; ++b) sum += cnt[b];
+    int32_t tot;
+    int32_t run = block_excl_scan<kBlock, int32_t>(sum, s_wave, tot);
+    for (int b = b0; b < b0 + per && b < nbk; ++b) {
+        const int32_t v = cnt[b];
+        cnt[b] = run;
+        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + blockIdx.x] - run;
+        run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int e = threadIdx.x + t * kBlock;
+        if (e < tn) order[cnt[bk[t]] + rk[t]] = (uint16_t)e;
+    }
+    __syncthreads();
+    // gather inside the tile (all loads of a group issued before any store)
+    constexpr int G = 4;
+    for (int p0 = threadIdx.x; p0 < tn; p0 += G * kBlock) {
+        int64_t i[G];
+        int key[G];
+        typename Mode<M>::Pay q[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int p = p0 + t * kBlock;
+            i[t] = c0 + order[p < tn ? p : tn - 1];
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            key[t] = box_id[i[t]];
+            q[t].x = (Real)x[i[t]];
+            q[t].y = (Real)y[i[t]];
+            q[t].z = (Real)z[i[t]];
+            q[t].w = (Real)0.5 * (Real)d[i[t]];
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int p = p0 + t * kBlock;
+            if (p < tn) {
+                const int pos = gcur[key[t] >> sb] + p;
+                key2[pos] = key[t];
+                idx2[pos] = (int32_t)i[t];
+                pay2[pos] = q[t];
+            }
+        }
     }
 }
 
 // -------------------------------------------------------------- bucket sort
 
 constexpr int kSortBoxes = 1 << kSBMax;
+constexpr int kSortStage = 8192;   // agents of a bucket whose output is staged in LDS
 
 template <int M>
 __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __restrict__ hdr,
@@ -425,6 +486,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              typename Mode<M>::Pay* __restrict__ pay)
 {
     __shared__ int32_t c[kSortBoxes];
+    __shared__ int32_t inv[kSortStage];      // final slot -> position in the bucket's input
     __shared__ int32_t s_wave[kSortThreads / kWave];
     if (hdr->error) return;
     const int b = blockIdx.x;
@@ -434,6 +496,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     const int b0 = b << sb;
     const int nbox = (int)((total - b0) < (1ll << sb) ? (total - b0) : (1ll << sb));
     const int s0 = bstart[b], s1 = bstart[b + 1];
+    const bool staged = (s1 - s0) <= kSortStage;
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
@@ -467,8 +530,20 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         const int be = s0 + c[k];
         int r = 0;
         for (int m = bs; m < be; ++m) r += (tmp[m] < orig) ? 1 : 0;
-        perm[bs + r] = orig;
-        pay[bs + r] = pay2[e];
+        if (staged) {
+            inv[bs + r - s0] = e - s0;
+        } else {
+            perm[bs + r] = orig;
+            pay[bs + r] = pay2[e];
+        }
+    }
+    if (!staged) return;   // block-uniform
+    __syncthreads();
+    // 5. write the sorted bucket in slot order
+    for (int p = threadIdx.x; p < s1 - s0; p += kSortThreads) {
+        const int e = s0 + inv[p];
+        perm[s0 + p] = idx2[e];
+        pay[s0 + p] = pay2[e];
     }
 }
 
