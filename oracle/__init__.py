@@ -32,6 +32,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mech_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+# A test may point the wrapper at another build of the oracle (the mutation
+# tests load deliberately broken copies to show the pins catch them).
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 _CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
            "-Wall", "-Wextra", "-Wno-unused-parameter"]
 _lock = threading.Lock()
@@ -59,8 +62,11 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            L = ctypes.CDLL(_LIB)
+            if _LIB_OVERRIDE:
+                L = ctypes.CDLL(_LIB_OVERRIDE)
+            else:
+                build()
+                L = ctypes.CDLL(_LIB)
             P = ctypes.c_void_p
             I64 = ctypes.c_int64
             D = ctypes.c_double
