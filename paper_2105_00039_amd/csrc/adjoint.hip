@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
     __shared__ uint32_t lst[kMaxContacts * kBlock];
+    __shared__ int2 tab[9 * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
     force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                         fx, fy, fz);
+                         tab + threadIdx.x, fx, fy, fz);
     const int32_t o = perm[k];
     const Real gx = gdx[o], gy = gdy[o], gz = gdz[o];
     const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
@@ -117,6 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
     using Pay = typename Mode<M>::Pay;
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
+    __shared__ uint32_t lst[kMaxContacts * kBlock];
+    __shared__ int2 tab[9 * kBlock];
     if (hdr->error) return;
     const unsigned vb = xcd_block();   // partials are indexed by this virtual block
     const int64_t k0 = (int64_t)vb * kBlock;
@@ -139,39 +142,37 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Pay pi = pay[k];
         const Pay fi = fbar[k];
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
+        const char* pbase = reinterpret_cast<const char*>(pay);
+        const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        for_each_run(g, c, start, [&](int j0, int j1) {
-            for (int j = j0; j < j1; ++j) {
-                const Pay q = pay[j];
-                const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-                const Real l2 = ux * ux + uy * uy + uz * uz;
-                const Real rs = pi.w + q.w;
-                if (l2 < rs * rs && l2 > (Real)0) {
-                    const Real l = fsqrt(l2);
-                    const Real delta = rs - l;
-                    if (delta > (Real)0) {
-                        const Pay fj = fbar[j];
-                        const Real il = (Real)1 / l;
-                        const Real ex = ux * il, ey = uy * il, ez = uz * il;
-                        const Real rho = pi.w * q.w / rs;
-                        const Real sq = fsqrt(rho * delta);
-                        const Real sv = kap * delta - gam * sq;
-                        const Real h = (Real)0.5 / sq;
-                        const Real s_d = kap - gam * rho * h;
-                        const Real s_r = -gam * delta * h;
-                        const Real wx = fi.x - fj.x, wy = fi.y - fj.y, wz = fi.z - fj.z;
-                        const Real qv = ex * wx + ey * wy + ez * wz;
-                        const Real sl = sv * il;
-                        px += sl * (wx - ex * qv) - s_d * qv * ex;
-                        py += sl * (wy - ey * qv) - s_d * qv * ey;
-                        pz += sl * (wz - ez * qv) - s_d * qv * ez;
-                        rb += qv * (s_d + s_r * (q.w * q.w) / (rs * rs));
-                        const Real eF = ex * fi.x + ey * fi.y + ez * fi.z;
-                        kbl += delta * eF;
-                        gbl -= sq * eF;
-                    }
-                }
-            }
+        scan_contacts<Real, Pay>(g, c, pi, start, pay, lst + threadIdx.x, tab + threadIdx.x,
+                                 [&](uint32_t off) {
+            const Pay q = *reinterpret_cast<const Pay*>(pbase + off);
+            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+            const Real l2 = ux * ux + uy * uy + uz * uz;
+            const Real rs = pi.w + q.w;
+            const Real l = fsqrt(l2);
+            const Real delta = rs - l;
+            if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
+            const Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
+            const Real il = (Real)1 / l;
+            const Real ex = ux * il, ey = uy * il, ez = uz * il;
+            const Real rho = pi.w * q.w / rs;
+            const Real sq = fsqrt(rho * delta);
+            const Real sv = kap * delta - gam * sq;
+            const Real h = (Real)0.5 / sq;
+            const Real s_d = kap - gam * rho * h;
+            const Real s_r = -gam * delta * h;
+            const Real wx = fi.x - fj.x, wy = fi.y - fj.y, wz = fi.z - fj.z;
+            const Real qv = ex * wx + ey * wy + ez * wz;
+            const Real sl = sv * il;
+            px += sl * (wx - ex * qv) - s_d * qv * ex;
+            py += sl * (wy - ey * qv) - s_d * qv * ey;
+            pz += sl * (wz - ez * qv) - s_d * qv * ez;
+            rb += qv * (s_d + s_r * (q.w * q.w) / (rs * rs));
+            const Real eF = ex * fi.x + ey * fi.y + ez * fi.z;
+            kbl += delta * eF;
+            gbl -= sq * eF;
         });
         const int32_t o = perm[k];
         gx[o] = px;

@@ -14,10 +14,12 @@ constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kScanItems = 8;         // items per thread in the neighbour-offset scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBoundsChunk = kBlock * 16;   // agents per block in the bounds pass
-constexpr int kTileA = kBlock * 16;   // agents per block in the bucket histogram/partition
+constexpr int kTileThreads = 1024;    // threads per block of the bucket histogram/partition
+constexpr int kTileA = 4096;          // agents per block in the bucket histogram/partition
 constexpr int kBucketsMax = 4096;     // bucket count limit of the two-level sort
-constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in [6, 13]
-constexpr int kSBMax = 13;
+constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in [6, 12]
+constexpr int kSBMax = 12;
+constexpr int kBucketAgents = 2048;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 
 // Device error bits (ms_grid_info.error and the workspace error word).

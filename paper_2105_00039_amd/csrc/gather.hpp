@@ -80,7 +80,7 @@ __device__ __forceinline__ unsigned xcd_block()
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-constexpr int kMaxContacts = 20;   // per-lane contact list length in LDS
+constexpr int kMaxContacts = 16;   // per-lane contact list length in LDS
 
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
@@ -164,61 +164,90 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     return R;
 }
 
+// Visit the candidates of agent `pi` that may touch it, in canonical order,
+// calling on_pair(offset) for each candidate that passes the cheap test
+// |u|^2 < (ri + rj)^2 (offset = byte offset of its payload).  The caller's
+// on_pair must still check delta > 0 and |u| > 0 (it sees the agent itself).
+//
+// The lane's non-empty trimmed runs are compacted into its column of an LDS
+// table (`tab`, stride kBlock) and scanned as one concatenated candidate
+// stream, so a wavefront iterates as often as its longest lane's total rather
+// than the sum over the 9 runs of the longest lane's run.  The next
+// candidate's load is issued before the current one is tested.  Passing
+// candidates are appended to this lane's list in LDS (`lst`, stride kBlock)
+// without branching (the slot is always written, the cursor advances on a
+// hit) and handed to on_pair in list order when the list is full and at the
+// end, so the pair work runs with the wavefront's lanes mostly busy and in the
+// candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
+// payload bytes.
+template <typename Real, typename Pay, typename OnPair>
+__device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
+                                              const int32_t* __restrict__ start,
+                                              const Pay* __restrict__ pay, uint32_t* lst,
+                                              int2* tab, OnPair&& on_pair)
+{
+    constexpr uint32_t P = (uint32_t)sizeof(Pay);
+    const char* base = reinterpret_cast<const char*>(pay);
+    int cnt = 0;
+    auto drain = [&]() {
+        for (int t = 0; t < cnt; ++t) on_pair(lst[t * kBlock]);
+        cnt = 0;
+    };
+    const Runs R = stencil_runs<Real>(g, c, start, pi.x, pi.y, pi.z, pi.w);
+    int nr = 0;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        if (R.e[r] > R.b[r]) {
+            tab[nr * kBlock] = make_int2(R.b[r] * (int)P, R.e[r] * (int)P);
+            ++nr;
+        }
+    }
+    if (nr > 0) {
+        int ri = 0;
+        const int2 t0 = tab[0];
+        uint32_t off = (uint32_t)t0.x, end = (uint32_t)t0.y;
+        Pay q = *reinterpret_cast<const Pay*>(base + off);
+        while (ri < nr) {
+            // position after this candidate, and the prefetch of its payload
+            uint32_t noff = off + P, nend = end;
+            int nri = ri;
+            if (noff == end) {
+                ++nri;
+                if (nri < nr) {
+                    const int2 t = tab[nri * kBlock];
+                    noff = (uint32_t)t.x;
+                    nend = (uint32_t)t.y;
+                }
+            }
+            const Pay qn = *reinterpret_cast<const Pay*>(base + (nri < nr ? noff : off));
+            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+            const Real l2 = ux * ux + uy * uy + uz * uz;
+            const Real rs = pi.w + q.w;
+            lst[cnt * kBlock] = off;
+            cnt += (l2 < rs * rs) ? 1 : 0;
+            if (cnt == kMaxContacts) drain();
+            q = qn;
+            off = noff;
+            end = nend;
+            ri = nri;
+        }
+    }
+    drain();
+}
+
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
-// order.  Two phases keep the wavefront busy.  The scan tests each candidate
-// with |u|^2 < (ri + rj)^2 only and appends its byte offset to this lane's
-// list in LDS (`lst`, stride kBlock) without branching: the slot is always
-// written and the cursor advances on a hit.  Four candidates are loaded
-// before any is tested (indices clamped into the run, surplus tests masked)
-// so four loads are in flight per lane.  The contact math then runs over the
-// list; it also drops the agent itself (|u| = 0).  A full list is drained
-// before the scan continues, so the sum follows the candidate order.
-// Offsets are 32-bit, so a workspace holds fewer than 2^32 payload bytes.
+// order (contact_force drops non-overlapping pairs and the agent itself).
 template <typename Real, typename Pay>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           const int32_t* __restrict__ start,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          uint32_t* lst, Real& fx, Real& fy, Real& fz)
+                                          uint32_t* lst, int2* tab, Real& fx, Real& fy, Real& fz)
 {
-    constexpr uint32_t P = (uint32_t)sizeof(Pay);
     const char* base = reinterpret_cast<const char*>(pay);
     Real ax = 0, ay = 0, az = 0;
-    int cnt = 0;
-    auto drain = [&]() {
-        for (int t = 0; t < cnt; ++t) {
-            const Pay q = *reinterpret_cast<const Pay*>(base + lst[t * kBlock]);
-            contact_force(pi, q, kap, gam, ax, ay, az);
-        }
-        cnt = 0;
-    };
-    auto test = [&](const Pay& q, uint32_t off, bool live) {
-        const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-        const Real l2 = ux * ux + uy * uy + uz * uz;
-        const Real rs = pi.w + q.w;
-        lst[cnt * kBlock] = off;
-        cnt += (live && l2 < rs * rs) ? 1 : 0;
-        if (cnt == kMaxContacts) drain();
-    };
-    const Runs R = stencil_runs<Real>(g, c, start, pi.x, pi.y, pi.z, pi.w);
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-        const uint32_t end = (uint32_t)R.e[r] * P;
-        const uint32_t last = end - P;
-        for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
-            const uint32_t o1 = off + P < end ? off + P : last;
-            const uint32_t o2 = off + 2 * P < end ? off + 2 * P : last;
-            const uint32_t o3 = off + 3 * P < end ? off + 3 * P : last;
-            const Pay q0 = *reinterpret_cast<const Pay*>(base + off);
-            const Pay q1 = *reinterpret_cast<const Pay*>(base + o1);
-            const Pay q2 = *reinterpret_cast<const Pay*>(base + o2);
-            const Pay q3 = *reinterpret_cast<const Pay*>(base + o3);
-            test(q0, off, true);
-            test(q1, o1, off + P < end);
-            test(q2, o2, off + 2 * P < end);
-            test(q3, o3, off + 3 * P < end);
-        }
-    }
-    drain();
+    scan_contacts<Real, Pay>(g, c, pi, start, pay, lst, tab, [&](uint32_t off) {
+        contact_force(pi, *reinterpret_cast<const Pay*>(base + off), kap, gam, ax, ay, az);
+    });
     fx = ax; fy = ay; fz = az;
 }
 

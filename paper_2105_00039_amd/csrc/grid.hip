@@ -267,8 +267,11 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         uint32_t err = s_err | hdr->off_err;
         hdr->off_err = 0u;
         if (running > max_boxes || running >= 2147483647ll) err |= ERR_CAPACITY;
+        // buckets of 2^sb boxes holding about kBucketAgents agents on average,
+        // and no more buckets than the workspace holds
         int sb = kSBMin;
-        while (sb < kSBMax && ((running + (1ll << sb) - 1) >> sb) > 1024) ++sb;
+        while (sb < kSBMax && (1ll << (sb + 1)) * n <= (long long)kBucketAgents * running) ++sb;
+        while (sb < kSBMax && ((running + (1ll << sb) - 1) >> sb) > nb_cap) ++sb;
         const long long nbk = (running + (1ll << sb) - 1) >> sb;
         if (nbk > nb_cap) err |= ERR_CAPACITY;
         hdr->need_boxes = running;
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
 // ------------------------------------------------------- bucket histogram
 
 template <int M, bool BATCHED>
-__global__ __launch_bounds__(kBlock) void k_hist(const typename Mode<M>::In* __restrict__ x,
+__global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::In* __restrict__ x,
                                                  const typename Mode<M>::In* __restrict__ y,
                                                  const typename Mode<M>::In* __restrict__ z,
                                                  int64_t n, const int64_t* __restrict__ off,
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const typename Mode<M>::In* __r
     __shared__ int s_range[2];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
-    for (int b = threadIdx.x; b < nbk; b += kBlock) h[b] = 0;
+    for (int b = threadIdx.x; b < nbk; b += kTileThreads) h[b] = 0;
     const int64_t c0 = (int64_t)blockIdx.x * kTileA;
     const int64_t c1 = (c0 + kTileA < n) ? c0 + kTileA : n;
     if (BATCHED && threadIdx.x == 0) {
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const typename Mode<M>::In* __r
         s_range[1] = find_sim(off, 0, B, c1 - 1);
     }
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kTileThreads) {
         const int s = BATCHED ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
         const SimGeom& g = geom[s];
         const int ix = axis_index((double)(Real)x[i], g.origin[0], g.edge, g.dims[0]);
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const typename Mode<M>::In* __r
         atomicAdd(&h[key >> sb], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbk; b += kBlock)
+    for (int b = threadIdx.x; b < nbk; b += kTileThreads)
         hist[(int64_t)b * gridDim.x + blockIdx.x] = h[b];
 }
 
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(1024) void k_bucketscan(const Header* __restrict__ 
 // contiguously (consecutive lanes -> consecutive addresses), reading the
 // agents' inputs inside the tile.
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In* __restrict__ x,
+__global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<M>::In* __restrict__ x,
                                                       const typename Mode<M>::In* __restrict__ y,
                                                       const typename Mode<M>::In* __restrict__ z,
                                                       const typename Mode<M>::In* __restrict__ d,
@@ -395,21 +398,21 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
                                                       typename Mode<M>::Pay* __restrict__ pay2)
 {
     using Real = typename Mode<M>::Real;
-    constexpr int IT = kTileA / kBlock;
+    constexpr int IT = kTileA / kTileThreads;
     __shared__ int32_t cnt[kBucketsMax];     // tile counts, then tile-local bucket starts
     __shared__ int32_t gcur[kBucketsMax];    // global start of this tile's run per bucket
     __shared__ uint16_t order[kTileA];       // tile-local index in bucket order
-    __shared__ int32_t s_wave[kBlock / kWave];
+    __shared__ int32_t s_wave[kTileThreads / kWave];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
-    for (int b = threadIdx.x; b < nbk; b += kBlock) cnt[b] = 0;
+    for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kTileA;
     const int tn = (int)((c0 + kTileA < n) ? kTileA : n - c0);
     int bk[IT], rk[IT];
 #pragma unroll
     for (int t = 0; t < IT; ++t) {
-        const int e = threadIdx.x + t * kBlock;
+        const int e = threadIdx.x + t * kTileThreads;
         bk[t] = -1;
         if (e < tn) {
             bk[t] = box_id[c0 + e] >> sb;
@@ -418,12 +421,12 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
     }
     __syncthreads();
     // exclusive scan of the tile counts over buckets; global run starts
-    const int per = (nbk + kBlock - 1) / kBlock;
+    const int per = (nbk + kTileThreads - 1) / kTileThreads;
     const int b0 = threadIdx.x * per;
     int32_t sum = 0;
     for (int b = b0; b < b0 + per && b < nbk; ++b) sum += cnt[b];
     int32_t tot;
-    int32_t run = block_excl_scan<kBlock, int32_t>(sum, s_wave, tot);
+    int32_t run = block_excl_scan<kTileThreads, int32_t>(sum, s_wave, tot);
     for (int b = b0; b < b0 + per && b < nbk; ++b) {
         const int32_t v = cnt[b];
         cnt[b] = run;
@@ -433,19 +436,19 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < IT; ++t) {
-        const int e = threadIdx.x + t * kBlock;
+        const int e = threadIdx.x + t * kTileThreads;
         if (e < tn) order[cnt[bk[t]] + rk[t]] = (uint16_t)e;
     }
     __syncthreads();
     // gather inside the tile (all loads of a group issued before any store)
     constexpr int G = 4;
-    for (int p0 = threadIdx.x; p0 < tn; p0 += G * kBlock) {
+    for (int p0 = threadIdx.x; p0 < tn; p0 += G * kTileThreads) {
         int64_t i[G];
         int key[G];
         typename Mode<M>::Pay q[G];
 #pragma unroll
         for (int t = 0; t < G; ++t) {
-            const int p = p0 + t * kBlock;
+            const int p = p0 + t * kTileThreads;
             i[t] = c0 + order[p < tn ? p : tn - 1];
         }
 #pragma unroll
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
-            const int p = p0 + t * kBlock;
+            const int p = p0 + t * kTileThreads;
             if (p < tn) {
                 const int pos = gcur[key[t] >> sb] + p;
                 key2[pos] = key[t];
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_partition(const typename Mode<M>::In
 // -------------------------------------------------------------- bucket sort
 
 constexpr int kSortBoxes = 1 << kSBMax;
-constexpr int kSortStage = 8192;   // agents of a bucket whose output is staged in LDS
+constexpr int kSortStage = 4096;   // buckets up to this many agents are sorted in LDS
 
 template <int M>
 __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __restrict__ hdr,
@@ -486,6 +489,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              typename Mode<M>::Pay* __restrict__ pay)
 {
     __shared__ int32_t c[kSortBoxes];
+    __shared__ int32_t mem[kSortStage];      // input indices of each box, in arrival order
     __shared__ int32_t inv[kSortStage];      // final slot -> position in the bucket's input
     __shared__ int32_t s_wave[kSortThreads / kWave];
     if (hdr->error) return;
@@ -497,6 +501,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     const int nbox = (int)((total - b0) < (1ll << sb) ? (total - b0) : (1ll << sb));
     const int s0 = bstart[b], s1 = bstart[b + 1];
     const bool staged = (s1 - s0) <= kSortStage;
+    int32_t* members = staged ? mem : tmp + s0;   // block-uniform
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
@@ -519,22 +524,22 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     // 3. agents into their box range (arrival order)
     for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
         const int slot = atomicAdd(&c[key2[e] - b0], 1);
-        tmp[s0 + slot] = idx2[e];
+        members[slot] = idx2[e];
     }
     __syncthreads();
     // 4. c[k] now holds the end of box k; rank among box mates by input index
     for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
         const int k = key2[e] - b0;
         const int32_t orig = idx2[e];
-        const int bs = s0 + (k > 0 ? c[k - 1] : 0);
-        const int be = s0 + c[k];
+        const int bs = k > 0 ? c[k - 1] : 0;
+        const int be = c[k];
         int r = 0;
-        for (int m = bs; m < be; ++m) r += (tmp[m] < orig) ? 1 : 0;
+        for (int m = bs; m < be; ++m) r += (members[m] < orig) ? 1 : 0;
         if (staged) {
-            inv[bs + r - s0] = e - s0;
+            inv[bs + r] = e - s0;
         } else {
-            perm[bs + r] = orig;
-            pay[bs + r] = pay2[e];
+            perm[s0 + bs + r] = orig;
+            pay[s0 + bs + r] = pay2[e];
         }
     }
     if (!staged) return;   // block-uniform
@@ -573,13 +578,15 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     k_boxbase<<<1, 1024, 0, s>>>(D.hdr, D.geom, B, n, L.max_boxes, L.nb_cap, D.start);
     const unsigned nba = (unsigned)((n + kTileA - 1) / kTileA);
     if (batched)
-        k_hist<M, true><<<nba, kBlock, 0, s>>>(x, y, z, n, woff, B, D.geom, D.hdr, D.box_id, D.hist);
+        k_hist<M, true><<<nba, kTileThreads, 0, s>>>(x, y, z, n, woff, B, D.geom, D.hdr, D.box_id,
+                                                     D.hist);
     else
-        k_hist<M, false><<<nba, kBlock, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr, D.box_id, D.hist);
+        k_hist<M, false><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr, D.box_id,
+                                                      D.hist);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
     k_bucketscan<<<1, 1024, 0, s>>>(D.hdr, btot, D.bstart);
-    k_partition<M><<<nba, kBlock, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.hist, D.bstart, D.key2,
+    k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.hist, D.bstart, D.key2,
                                           D.idx2, static_cast<Pay*>(D.pay2));
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
         D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), D.bstart, D.start, D.tmp, D.perm,
