@@ -45,7 +45,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
     __shared__ uint32_t lst[kMaxContacts * kBlock];
-    __shared__ int2 tab[9 * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
@@ -57,8 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                         tab + threadIdx.x, fx, fy, fz);
+    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+                         (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                         fx, fy, fz);
     const int32_t o = perm[k];
     const Real gx = gdx[o], gy = gdy[o], gz = gdz[o];
     const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
@@ -119,7 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
     __shared__ uint32_t lst[kMaxContacts * kBlock];
-    __shared__ int2 tab[9 * kBlock];
     if (hdr->error) return;
     const unsigned vb = xcd_block();   // partials are indexed by this virtual block
     const int64_t k0 = (int64_t)vb * kBlock;
@@ -142,19 +141,20 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Pay pi = pay[k];
         const Pay fi = fbar[k];
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
-        const char* pbase = reinterpret_cast<const char*>(pay);
         const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        scan_contacts<Real, Pay>(g, c, pi, start, pay, lst + threadIdx.x, tab + threadIdx.x,
-                                 [&](uint32_t off) {
-            const Pay q = *reinterpret_cast<const Pay*>(pbase + off);
+        scan_contacts<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+                                 lst + threadIdx.x,
+                                 [&](uint32_t off, const Pay& q) {
+            // loaded before the contact test so a group's loads overlap
+            Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
+            pin(fj);
             const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
             const Real l2 = ux * ux + uy * uy + uz * uz;
             const Real rs = pi.w + q.w;
             const Real l = fsqrt(l2);
             const Real delta = rs - l;
             if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
-            const Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
             const Real il = (Real)1 / l;
             const Real ex = ux * il, ey = uy * il, ez = uz * il;
             const Real rho = pi.w * q.w / rs;

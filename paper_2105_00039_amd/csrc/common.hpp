@@ -229,4 +229,17 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
+// Virtual block index that gives each XCD a contiguous share of the blocks.
+// Work-groups are dispatched round-robin over the 8 XCDs, so block b runs on
+// XCD b % 8; mapping those blocks to one contiguous range keeps the data that
+// neighbouring virtual blocks share (candidate rows of the force gather,
+// partially written cache lines of the partition's bucket runs) in the L2 of
+// one XCD.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 }  // namespace ms

@@ -29,7 +29,6 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
     __shared__ uint32_t lst[kMaxContacts * kBlock];
-    __shared__ int2 tab[9 * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
@@ -41,8 +40,9 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, start, pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                         tab + threadIdx.x, fx, fy, fz);
+    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+                         (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                         fx, fy, fz);
     Real ddx, ddy, ddz;
     displacement<Real>(fx, fy, fz, (Real)P.dt, (Real)P.max_disp, (Real)P.adherence, ddx, ddy, ddz);
     const int32_t o = perm[k];

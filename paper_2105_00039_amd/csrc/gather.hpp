@@ -37,6 +37,24 @@ __device__ __forceinline__ int block_sim(const int64_t* __restrict__ off, int32_
 
 struct Cell { int ix, iy, iz; };
 
+// Materialise a loaded value at this point of the program.  The compiler
+// otherwise sinks a load into the only branch that consumes it, which
+// serialises loads meant to be in flight together.
+__device__ __forceinline__ void pin4(uint32_t (&v)[4])
+{
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+template <typename Pay>
+__device__ __forceinline__ void pin4(Pay (&q)[4])
+{
+    asm volatile("" : "+v"(q[0].x), "+v"(q[0].y), "+v"(q[0].z), "+v"(q[0].w),
+                      "+v"(q[1].x), "+v"(q[1].y), "+v"(q[1].z), "+v"(q[1].w),
+                      "+v"(q[2].x), "+v"(q[2].y), "+v"(q[2].z), "+v"(q[2].w),
+                      "+v"(q[3].x), "+v"(q[3].y), "+v"(q[3].z), "+v"(q[3].w));
+}
+__device__ __forceinline__ void pin(F4& q) { asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z), "+v"(q.w)); }
+__device__ __forceinline__ void pin(D4& q) { asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z), "+v"(q.w)); }
+
 // Box coordinates of a position: the same FP64 binning as the grid build.
 template <typename Real>
 __device__ __forceinline__ Cell cell_of(const SimGeom& g, Real x, Real y, Real z)
@@ -69,18 +87,7 @@ __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int
     }
 }
 
-// Virtual block index that gives each XCD a contiguous share of the sorted
-// agents.  Work-groups are dispatched round-robin over the 8 XCDs, so block b
-// runs on XCD b % 8; mapping those blocks to one contiguous range keeps the
-// candidate rows a block reads in the L2 of the XCD that reads them.
-__device__ __forceinline__ unsigned xcd_block()
-{
-    const unsigned nb = gridDim.x, b = blockIdx.x;
-    const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
-constexpr int kMaxContacts = 16;   // per-lane contact list length in LDS
+constexpr int kMaxContacts = 32;   // per-lane contact list length in LDS
 
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
@@ -157,79 +164,84 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
         const int x0 = (c.ix > 0 && lx * lx + yz < r2) ? c.ix - 1 : c.ix;
         const int x1 = (c.ix + 1 < nx && hx * hx + yz < r2) ? c.ix + 1 : c.ix;
         const int row = g.box_base + (cz * ny + cy) * nx;
-        const int i0 = ok ? row + x0 : 0, i1 = ok ? row + x1 + 1 : 0;
-        R.b[r] = start[i0];
-        R.e[r] = ok ? start[i1] : R.b[r];
+        // Out-of-range rows read start[0] twice (an empty run), so all 18
+        // loads are unconditional and issue back to back.
+        R.b[r] = start[ok ? row + x0 : 0];
+        R.e[r] = start[ok ? row + x1 + 1 : 0];
     }
     return R;
 }
 
 // Visit the candidates of agent `pi` that may touch it, in canonical order,
-// calling on_pair(offset) for each candidate that passes the cheap test
-// |u|^2 < (ri + rj)^2 (offset = byte offset of its payload).  The caller's
-// on_pair must still check delta > 0 and |u| > 0 (it sees the agent itself).
+// calling on_pair(offset, payload) for each candidate that passes the cheap
+// test |u|^2 < (ri + rj)^2 (offset = byte offset of its payload, self_off
+// that of the agent itself).  The caller's on_pair must still check
+// delta > 0 and |u| > 0: it sees the agent itself, and the list is handed
+// over in groups of four padded with the agent's own entry.
 //
-// The lane's non-empty trimmed runs are compacted into its column of an LDS
-// table (`tab`, stride kBlock) and scanned as one concatenated candidate
-// stream, so a wavefront iterates as often as its longest lane's total rather
-// than the sum over the 9 runs of the longest lane's run.  The next
-// candidate's load is issued before the current one is tested.  Passing
-// candidates are appended to this lane's list in LDS (`lst`, stride kBlock)
-// without branching (the slot is always written, the cursor advances on a
-// hit) and handed to on_pair in list order when the list is full and at the
-// end, so the pair work runs with the wavefront's lanes mostly busy and in the
-// candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
+// Two phases keep the wavefront busy.  The scan walks the 9 trimmed runs;
+// four candidates are loaded before any is tested (offsets clamped into the
+// run, surplus tests masked), and each passing candidate's offset is appended
+// to this lane's list in LDS (`lst`, stride kBlock) without branching (the
+// slot is always written, the cursor advances on a hit).  The pair work then
+// runs over the list, four payload loads in flight at a time.  The list is
+// drained before a group of four could overflow it, so pairs are handed over
+// in candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
 // payload bytes.
 template <typename Real, typename Pay, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
+                                              uint32_t self_off,
                                               const int32_t* __restrict__ start,
                                               const Pay* __restrict__ pay, uint32_t* lst,
-                                              int2* tab, OnPair&& on_pair)
+                                              OnPair&& on_pair)
 {
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
+    static_assert(kMaxContacts % 4 == 0, "the list drains in groups of four");
     const char* base = reinterpret_cast<const char*>(pay);
     int cnt = 0;
     auto drain = [&]() {
-        for (int t = 0; t < cnt; ++t) on_pair(lst[t * kBlock]);
+        for (int t = 0; t < cnt; t += 4) {
+            uint32_t o[4];
+            Pay q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t v = lst[(t + u) * kBlock];
+                o[u] = (t + u < cnt) ? v : self_off;
+            }
+            pin4(o);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = *reinterpret_cast<const Pay*>(base + o[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) on_pair(o[u], q[u]);
+        }
         cnt = 0;
     };
+    auto test = [&](Pay q, uint32_t off, bool live) {
+        pin(q);
+        const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+        const Real l2 = ux * ux + uy * uy + uz * uz;
+        const Real rs = pi.w + q.w;
+        lst[cnt * kBlock] = off;
+        cnt += (int)(live & (l2 < rs * rs));
+    };
     const Runs R = stencil_runs<Real>(g, c, start, pi.x, pi.y, pi.z, pi.w);
-    int nr = 0;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-        if (R.e[r] > R.b[r]) {
-            tab[nr * kBlock] = make_int2(R.b[r] * (int)P, R.e[r] * (int)P);
-            ++nr;
-        }
-    }
-    if (nr > 0) {
-        int ri = 0;
-        const int2 t0 = tab[0];
-        uint32_t off = (uint32_t)t0.x, end = (uint32_t)t0.y;
-        Pay q = *reinterpret_cast<const Pay*>(base + off);
-        while (ri < nr) {
-            // position after this candidate, and the prefetch of its payload
-            uint32_t noff = off + P, nend = end;
-            int nri = ri;
-            if (noff == end) {
-                ++nri;
-                if (nri < nr) {
-                    const int2 t = tab[nri * kBlock];
-                    noff = (uint32_t)t.x;
-                    nend = (uint32_t)t.y;
-                }
-            }
-            const Pay qn = *reinterpret_cast<const Pay*>(base + (nri < nr ? noff : off));
-            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-            const Real l2 = ux * ux + uy * uy + uz * uz;
-            const Real rs = pi.w + q.w;
-            lst[cnt * kBlock] = off;
-            cnt += (l2 < rs * rs) ? 1 : 0;
-            if (cnt == kMaxContacts) drain();
-            q = qn;
-            off = noff;
-            end = nend;
-            ri = nri;
+        const uint32_t end = (uint32_t)R.e[r] * P;
+        const uint32_t last = end - P;
+        for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
+            if (cnt > kMaxContacts - 4) drain();
+            const uint32_t o1 = off + P < end ? off + P : last;
+            const uint32_t o2 = off + 2 * P < end ? off + 2 * P : last;
+            const uint32_t o3 = off + 3 * P < end ? off + 3 * P : last;
+            const Pay q0 = *reinterpret_cast<const Pay*>(base + off);
+            const Pay q1 = *reinterpret_cast<const Pay*>(base + o1);
+            const Pay q2 = *reinterpret_cast<const Pay*>(base + o2);
+            const Pay q3 = *reinterpret_cast<const Pay*>(base + o3);
+            test(q0, off, true);
+            test(q1, o1, off + P < end);
+            test(q2, o2, off + 2 * P < end);
+            test(q3, o3, off + 3 * P < end);
         }
     }
     drain();
@@ -239,14 +251,13 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 // order (contact_force drops non-overlapping pairs and the agent itself).
 template <typename Real, typename Pay>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
-                                          const int32_t* __restrict__ start,
+                                          uint32_t self_off, const int32_t* __restrict__ start,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          uint32_t* lst, int2* tab, Real& fx, Real& fy, Real& fz)
+                                          uint32_t* lst, Real& fx, Real& fy, Real& fz)
 {
-    const char* base = reinterpret_cast<const char*>(pay);
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay>(g, c, pi, start, pay, lst, tab, [&](uint32_t off) {
-        contact_force(pi, *reinterpret_cast<const Pay*>(base + off), kap, gam, ax, ay, az);
+    scan_contacts<Real, Pay>(g, c, pi, self_off, start, pay, lst, [&](uint32_t, const Pay& q) {
+        contact_force(pi, q, kap, gam, ax, ay, az);
     });
     fx = ax; fy = ay; fz = az;
 }

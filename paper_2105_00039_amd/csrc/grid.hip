@@ -304,7 +304,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) h[b] = 0;
-    const int64_t c0 = (int64_t)blockIdx.x * kTileA;
+    const unsigned tile = xcd_block();
+    const int64_t c0 = (int64_t)tile * kTileA;
     const int64_t c1 = (c0 + kTileA < n) ? c0 + kTileA : n;
     if (BATCHED && threadIdx.x == 0) {
         s_range[0] = find_sim(off, 0, B, c0);
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbk; b += kTileThreads)
-        hist[(int64_t)b * gridDim.x + blockIdx.x] = h[b];
+        hist[(int64_t)b * gridDim.x + tile] = h[b];
 }
 
 // One block per bucket: exclusive scan along its row of per-block counts.
@@ -407,7 +408,8 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     const int sb = hdr->sb, nbk = hdr->nb;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kTileA;
+    const unsigned tile = xcd_block();   // consecutive tiles on one XCD
+    const int64_t c0 = (int64_t)tile * kTileA;
     const int tn = (int)((c0 + kTileA < n) ? kTileA : n - c0);
     int bk[IT], rk[IT];
 #pragma unroll
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     for (int b = b0; b < b0 + per && b < nbk; ++b) {
         const int32_t v = cnt[b];
         cnt[b] = run;
-        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + blockIdx.x] - run;
+        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + tile] - run;
         run += v;
     }
     __syncthreads();
