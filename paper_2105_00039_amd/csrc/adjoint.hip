@@ -31,6 +31,7 @@ namespace {
 template <int M, bool BATCHED>
 __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay* __restrict__ pay,
                                                      const int32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ split,
                                                      const int32_t* __restrict__ perm,
                                                      const SimGeom* __restrict__ geom,
                                                      const int64_t* __restrict__ off, int32_t B,
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                          (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                          fx, fy, fz);
     const int32_t o = perm[k];
@@ -102,6 +103,7 @@ template <int M, bool BATCHED>
 __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::Pay* __restrict__ pay,
                                                        const typename Mode<M>::Pay* __restrict__ fbar,
                                                        const int32_t* __restrict__ start,
+                                                       const uint32_t* __restrict__ split,
                                                        const int32_t* __restrict__ perm,
                                                        const SimGeom* __restrict__ geom,
                                                        const int64_t* __restrict__ off, int32_t B,
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
         const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        scan_contacts<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+        scan_contacts<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                                  lst + threadIdx.x,
                                  [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
@@ -246,16 +248,16 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
     Real *OX = (Real*)gx, *OY = (Real*)gy, *OZ = (Real*)gz, *OD = (Real*)gd;
     ms_params dummy{};
     if (batched) {
-        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, D.off, B, n, dummy,
+        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
                                                    p_dev, D.hdr, GX, GY, GZ, fb);
-        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.perm, D.geom, D.off, B, n,
+        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B, n,
                                                      dummy, p_dev, D.hdr, OX, OY, OZ, OD,
                                                      D.partials);
         k_reduce_params<<<B, kBlock, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
-        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, nullptr, 1, n,
+        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
                                                     *p_host, nullptr, D.hdr, GX, GY, GZ, fb);
-        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.perm, D.geom, nullptr, 1,
+        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                       n, *p_host, nullptr, D.hdr, OX, OY, OZ, OD,
                                                       D.partials);
         k_reduce_params<<<1, kBlock, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);

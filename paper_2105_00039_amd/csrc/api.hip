@@ -303,7 +303,8 @@ ms_status ms_grid_get(const ms_workspace* ws, ms_grid_info* info, int32_t* box_i
     if (box_id) e = hipMemcpyAsync(box_id, D.box_id, 4 * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && box_start)
         e = hipMemcpyAsync(box_start, D.start, 4 * (h.total_boxes + 1), hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && perm) e = hipMemcpyAsync(perm, D.perm, 4 * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && perm) e = ms::launch_canon(L, D, n, s);
+    if (e == hipSuccess && perm) e = hipMemcpyAsync(perm, D.canon, 4 * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return check_hip(e, who);
 }
@@ -329,7 +330,9 @@ ms_status ms_neighbors(const ms_workspace* ws, int32_t* counts, int64_t* offsets
     if (n == 0) {
         e = hipMemcpyAsync(offsets, &tot, 8, hipMemcpyHostToDevice, s);
     } else {
-        e = ms::launch_neighbors_count(L, D, n, ws->n_sims, batched, counts, offsets, s);
+        e = ms::launch_canon(L, D, n, s);
+        if (e == hipSuccess)
+            e = ms::launch_neighbors_count(L, D, n, ws->n_sims, batched, counts, offsets, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&tot, offsets + n, 8, hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -78,8 +78,8 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
-    size_t hdr, geom, off, bpart, box_id, start, hist, bstart, key2, idx2, pay2, tmp, perm,
-        payload, fbar, partials, scratch64, total;
+    size_t hdr, geom, off, bpart, box_id, quarter, start, split, hist, bstart, key2, idx2, pay2,
+        tmp, perm, payload, fbar, partials, scratch64, total;
     int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
@@ -109,7 +109,9 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     L.off = take(8 * (size_t)(max_sims + 1));
     L.bpart = take(sizeof(BoundsPart) * (size_t)(L.nblk_b_max + max_sims + 1));
     L.box_id = take(4 * (size_t)na);
+    L.quarter = take((size_t)na);
     L.start = take(4 * (size_t)(max_boxes + 2));
+    L.split = take(4 * (size_t)(max_boxes + 2));
     L.hist = take(4 * (size_t)(L.nb_cap * L.nblk_a_max));
     L.bstart = take(4 * (size_t)(2 * L.nb_cap + 2));
     L.key2 = take(4 * (size_t)na);
@@ -117,7 +119,8 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     L.pay2 = take(pay * (size_t)na);
     L.tmp = take(4 * (size_t)na);
     L.perm = take(4 * (size_t)na);
-    L.payload = take(pay * (size_t)na);
+    // three extra entries: the gather reads up to three slots past a run's end
+    L.payload = take(pay * (size_t)(na + 3));
     L.fbar = take(pay * (size_t)na);
     L.partials = take(16 * (size_t)L.n_part);
     // int64 scratch for the neighbour-offset scan: one entry per scan tile of n+1 items
@@ -132,15 +135,22 @@ struct Dev {
     SimGeom* geom;
     int64_t* off;
     BoundsPart* bpart;
-    int32_t* box_id;
-    int32_t* start;
+    int32_t* box_id;    // box index per agent, caller order
+    uint8_t* quarter;   // x-quarter of each agent inside its box, caller order
+    int32_t* start;     // box start offsets [total boxes + 1]
+    uint32_t* split;    // per box: quarter split offsets (split_word)
     int32_t* hist;      // [bucket][block-A] histogram, scanned in place along each row
     int32_t* bstart;    // [0, nb]: bucket starts; [nb_cap+1 ...]: bucket totals
-    int32_t* key2;
-    int32_t* idx2;
+    int32_t* key2;      // build: (box in bucket) << 2 | quarter, bucket order
+    int32_t* idx2;      // build: input index, bucket order
     void* pay2;
     int32_t* tmp;
-    int32_t* perm;
+    int32_t* perm;      // input index of each slot; slots ordered by (box, quarter, input index)
+    // After a build key2 / idx2 are free; the exports reuse them for the
+    // canonical order (box, input index): canon[c] = input index of canonical
+    // slot c, cslot[c] = the payload slot holding it.
+    int32_t* canon;
+    int32_t* cslot;
     void* payload;
     void* fbar;
     double* partials;
@@ -156,7 +166,9 @@ inline Dev resolve(const Layout& L, void* base)
     d.off = reinterpret_cast<int64_t*>(b + L.off);
     d.bpart = reinterpret_cast<BoundsPart*>(b + L.bpart);
     d.box_id = reinterpret_cast<int32_t*>(b + L.box_id);
+    d.quarter = reinterpret_cast<uint8_t*>(b + L.quarter);
     d.start = reinterpret_cast<int32_t*>(b + L.start);
+    d.split = reinterpret_cast<uint32_t*>(b + L.split);
     d.hist = reinterpret_cast<int32_t*>(b + L.hist);
     d.bstart = reinterpret_cast<int32_t*>(b + L.bstart);
     d.key2 = reinterpret_cast<int32_t*>(b + L.key2);
@@ -164,6 +176,8 @@ inline Dev resolve(const Layout& L, void* base)
     d.pay2 = b + L.pay2;
     d.tmp = reinterpret_cast<int32_t*>(b + L.tmp);
     d.perm = reinterpret_cast<int32_t*>(b + L.perm);
+    d.canon = d.idx2;
+    d.cslot = d.key2;
     d.payload = b + L.payload;
     d.fbar = b + L.fbar;
     d.partials = reinterpret_cast<double*>(b + L.partials);
@@ -191,6 +205,34 @@ __device__ __forceinline__ int axis_index(double p, double o, double e, int dim)
     double q = floor((p - o) / e);
     int i = (q > 0.0) ? (int)q : 0;
     return i < dim - 1 ? i : dim - 1;
+}
+
+// Quarter of the box ix (along one axis) that holds coordinate p:
+// floor(((p - o) - ix e) * (4/e)), clamped to [0, 3]; c4 = 4/e.  The grid
+// build files every agent by it; the gather only needs it to within a small
+// error, because it widens the bounds it looks up (see stencil_runs).
+__device__ __forceinline__ int box_quarter(double p, double o, double c4, double e, int ix)
+{
+    const double t = floor(((p - o) - (double)ix * e) * c4);
+    const int q = (t > 0.0) ? (int)t : 0;
+    return q < 3 ? q : 3;
+}
+
+// Per-box split word: bytes 0..2 hold the number of the box's agents in
+// quarters below 1, 2, 3 (the slot offsets where quarters 1, 2, 3 begin), byte 3
+// the box's agent count.  Boxes with more than 255 agents store kSplitNone and
+// are not trimmed inside.
+constexpr uint32_t kSplitNone = 0xffffffffu;
+
+// Slots of box (word w) to skip at its start when the row interval begins in
+// quarter q, and to drop at its end when it ends in quarter q.
+__device__ __forceinline__ int split_skip(uint32_t w, int q)
+{
+    return (q == 0 || w == kSplitNone) ? 0 : (int)((w >> (8 * (q - 1))) & 0xffu);
+}
+__device__ __forceinline__ int split_cut(uint32_t w, int q)
+{
+    return (q == 3 || w == kSplitNone) ? 0 : (int)((w >> 24) - ((w >> (8 * q)) & 0xffu));
 }
 
 // Simulation owning index k of a concatenation with offsets off[0..B]:

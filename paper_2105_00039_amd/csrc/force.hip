@@ -16,6 +16,7 @@ namespace {
 template <int M, bool BATCHED>
 __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
                                                   const int32_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ split,
                                                   const int32_t* __restrict__ perm,
                                                   const SimGeom* __restrict__ geom,
                                                   const int64_t* __restrict__ off, int32_t B,
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, pay,
+    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                          (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                          fx, fy, fz);
     Real ddx, ddy, ddz;
@@ -67,11 +68,15 @@ __global__ __launch_bounds__(kBlock) void k_integrate(PT* __restrict__ x, PT* __
 
 // Neighbour sets with the FP64 predicate |p_j - p_i|^2 < edge^2, the square
 // evaluated as (ux*ux + uy*uy) + uz*uz with no fused multiply-add so that it
-// is reproducible bit for bit.
+// is reproducible bit for bit.  Candidates are visited in canonical order
+// (ascending box, then input index) through cslot, the payload slot of each
+// canonical slot; list entries are input indices (canon).
 template <int M, bool BATCHED, bool FILL>
 __global__ __launch_bounds__(kBlock) void k_neighbors(const typename Mode<M>::Pay* __restrict__ pay,
                                                       const int32_t* __restrict__ start,
                                                       const int32_t* __restrict__ perm,
+                                                      const int32_t* __restrict__ canon,
+                                                      const int32_t* __restrict__ cslot,
                                                       const SimGeom* __restrict__ geom,
                                                       const int64_t* __restrict__ off, int32_t B,
                                                       int64_t n, const Header* __restrict__ hdr,
@@ -97,13 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const typename Mode<M>::Pa
     int64_t cnt = 0;
     const int64_t base = FILL ? offsets[me] : 0;
     for_each_run(g, c, start, [&](int j0, int j1) {
-        for (int j = j0; j < j1; ++j) {
+        for (int cc = j0; cc < j1; ++cc) {
+            const int j = cslot[cc];
             if (j == (int)k) continue;
             const Pay q = pay[j];
             const double ux = (double)q.x - xi, uy = (double)q.y - yi, uz = (double)q.z - zi;
             const double d2 = (ux * ux + uy * uy) + uz * uz;
             if (d2 < e2) {
-                if (FILL) list[base + cnt] = perm[j];
+                if (FILL) list[base + cnt] = canon[cc];
                 ++cnt;
             }
         }
@@ -215,10 +221,10 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
     Real* Z = static_cast<Real*>(dz);
     if (batched) {
         ms_params dummy{};
-        k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, D.off, B, n, dummy,
+        k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
                                                 p_dev, D.hdr, X, Y, Z);
     } else {
-        k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, nullptr, 1, n,
+        k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
                                                  *p_host, nullptr, D.hdr, X, Y, Z);
     }
     return hipGetLastError();
@@ -234,10 +240,12 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
     const int64_t* off = batched ? D.off : nullptr;
     if (!fill) {
         if (batched)
-            k_neighbors<M, true, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, B,
+            k_neighbors<M, true, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.canon, D.cslot,
+                                                               D.geom, off, B,
                                                                n, D.hdr, counts, nullptr, nullptr);
         else
-            k_neighbors<M, false, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, 1,
+            k_neighbors<M, false, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.canon, D.cslot,
+                                                                D.geom, off, 1,
                                                                 n, D.hdr, counts, nullptr, nullptr);
         const int64_t ntiles = (n + 1 + kScanTile - 1) / kScanTile;
         k_tile_sums<<<(unsigned)ntiles, kBlock, 0, s>>>(counts, n, D.scratch64);
@@ -245,10 +253,12 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
         k_tile_scan<<<(unsigned)ntiles, kBlock, 0, s>>>(counts, n, D.scratch64, offsets);
     } else {
         if (batched)
-            k_neighbors<M, true, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, B, n,
+            k_neighbors<M, true, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.canon, D.cslot,
+                                                              D.geom, off, B, n,
                                                               D.hdr, nullptr, offsets, list);
         else
-            k_neighbors<M, false, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.geom, off, 1,
+            k_neighbors<M, false, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.perm, D.canon, D.cslot,
+                                                               D.geom, off, 1,
                                                                n, D.hdr, nullptr, offsets, list);
     }
     return hipGetLastError();

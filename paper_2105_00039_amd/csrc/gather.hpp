@@ -129,20 +129,26 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
 }
 
 // The 9 runs of the stencil for the force sums, all bounds loaded up front
-// (one memory round trip), trimmed to the boxes the agent can touch: a
-// partner is at most e/2 in radius (the edge is at least the largest
-// diameter), so a contact lies within reach = r_i + e/2 of the centre.  A
-// (dy, dz) row whose y-z distance from the agent is >= reach is skipped, and
-// the first / last box of a run is dropped when its x distance (combined
-// with the row's y-z distance) is >= reach.  Distances are the agent's
-// offsets from its own box faces, in FP64, with a relative margin of 1e-9 on
-// reach, so no box holding a contact is ever dropped.  Out-of-range rows give
-// empty runs.
+// (one memory round trip), trimmed to the agents the sphere of reach
+// r_i + e/2 around the agent can touch: a partner is at most e/2 in radius
+// (the edge is at least the largest diameter), so every contact lies inside
+// it.  A (dy, dz) row whose y-z distance from the agent is >= reach is
+// skipped.  Otherwise the row can only hold contacts with |x_j - x_i| < w,
+// w = sqrt(reach^2 - yz^2): the run starts in the box holding x_i - w and
+// ends in the box holding x_i + w, and inside those two boxes the agents of
+// the quarters wholly outside the interval are dropped (a box's agents are
+// ordered by x-quarter; the split word gives where each quarter begins).
+// The row and box decisions are FP64 (offsets of the agent from its own box
+// faces; reach carries a relative margin of 1e-9).  The quarters of the
+// interval ends are located in FP32 with w widened by 1e-5 e, far above the
+// FP32 error of those positions (< 2e-7 e), so no quarter holding a contact
+// is ever dropped.  Out-of-range rows give empty runs.
 struct Runs { int b[9], e[9]; };
 
 template <typename Real>
 __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
-                                             const int32_t* __restrict__ start, Real px, Real py,
+                                             const int32_t* __restrict__ start,
+                                             const uint32_t* __restrict__ split, Real px, Real py,
                                              Real pz, Real ri)
 {
     const int nx = g.dims[0], ny = g.dims[1], nz = g.dims[2];
@@ -153,21 +159,54 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     const double lx = ((double)px - g.origin[0]) - c.ix * e, hx = e - lx;
     const double ly = ((double)py - g.origin[1]) - c.iy * e, hy = e - ly;
     const double lz = ((double)pz - g.origin[2]) - c.iz * e, hz = e - lz;
+    const double lx2 = lx * lx, hx2 = hx * hx;
     const double dy2[3] = {ly * ly, 0.0, hy * hy};
     const double dz2[3] = {lz * lz, 0.0, hz * hz};
-    Runs R;
+    const float ef = (float)e, c4 = 4.0f / ef, lxf = (float)lx, pad = 1e-5f * ef;
+    const int rowc = g.box_base + (c.iz * ny + c.iy) * nx, plane = nx * ny;
+    uint32_t i0[9], i1[9];
+    int qa[9], qb[9];
+    bool okr[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const int cz = c.iz + r / 3 - 1, cy = c.iy + r % 3 - 1;
         const double yz = dz2[r / 3] + dy2[r % 3];
         const bool ok = cz >= 0 && cz < nz && cy >= 0 && cy < ny && yz < r2;
-        const int x0 = (c.ix > 0 && lx * lx + yz < r2) ? c.ix - 1 : c.ix;
-        const int x1 = (c.ix + 1 < nx && hx * hx + yz < r2) ? c.ix + 1 : c.ix;
-        const int row = g.box_base + (cz * ny + cy) * nx;
-        // Out-of-range rows read start[0] twice (an empty run), so all 18
-        // loads are unconditional and issue back to back.
-        R.b[r] = start[ok ? row + x0 : 0];
-        R.e[r] = start[ok ? row + x1 + 1 : 0];
+        const bool lo_prev = c.ix > 0 && lx2 + yz < r2;        // interval reaches box ix-1
+        const bool hi_next = c.ix + 1 < nx && hx2 + yz < r2;   // interval reaches box ix+1
+        const float w = __builtin_amdgcn_sqrtf((float)(r2 - yz)) + pad;
+        // interval ends relative to the lower face of the box they are looked up in
+        const float rlo = lxf - w + (lo_prev ? ef : 0.0f);
+        const float rhi = lxf + w - (hi_next ? ef : 0.0f);
+        const int ta = (int)floorf(rlo * c4), tb = (int)floorf(rhi * c4);
+        const int row = rowc + (r / 3 - 1) * plane + (r % 3 - 1) * nx;
+        okr[r] = ok;
+        // Byte offsets of the two end boxes (32-bit, from a scalar base).
+        // Out-of-range rows read box 0 (an empty run), so all loads are
+        // unconditional and issue back to back.
+        i0[r] = ok ? 4u * (uint32_t)(row + (lo_prev ? c.ix - 1 : c.ix)) : 0u;
+        i1[r] = ok ? 4u * (uint32_t)(row + (hi_next ? c.ix + 1 : c.ix)) : 0u;
+        qa[r] = ta < 0 ? 0 : (ta > 3 ? 3 : ta);
+        qb[r] = tb < 0 ? 0 : (tb > 3 ? 3 : tb);
+    }
+    int sa[9], sb[9];
+    uint32_t wa[9], wb[9];
+    const char* sbase = reinterpret_cast<const char*>(start);
+    const char* wbase = reinterpret_cast<const char*>(split);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        sa[r] = *reinterpret_cast<const int32_t*>(sbase + i0[r]);
+        sb[r] = *reinterpret_cast<const int32_t*>(sbase + i1[r] + 4u);
+        wa[r] = *reinterpret_cast<const uint32_t*>(wbase + i0[r]);
+        wb[r] = *reinterpret_cast<const uint32_t*>(wbase + i1[r]);
+    }
+    Runs R;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const int b = sa[r] + split_skip(wa[r], qa[r]);
+        const int en = sb[r] - split_cut(wb[r], qb[r]);
+        R.b[r] = b;
+        R.e[r] = (okr[r] && en > b) ? en : b;
     }
     return R;
 }
@@ -192,6 +231,7 @@ template <typename Real, typename Pay, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
+                                              const uint32_t* __restrict__ split,
                                               const Pay* __restrict__ pay, uint32_t* lst,
                                               OnPair&& on_pair)
 {
@@ -224,24 +264,23 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
         lst[cnt * kBlock] = off;
         cnt += (int)(live & (l2 < rs * rs));
     };
-    const Runs R = stencil_runs<Real>(g, c, start, pi.x, pi.y, pi.z, pi.w);
+    const Runs R = stencil_runs<Real>(g, c, start, split, pi.x, pi.y, pi.z, pi.w);
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const uint32_t end = (uint32_t)R.e[r] * P;
-        const uint32_t last = end - P;
         for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
             if (cnt > kMaxContacts - 4) drain();
-            const uint32_t o1 = off + P < end ? off + P : last;
-            const uint32_t o2 = off + 2 * P < end ? off + 2 * P : last;
-            const uint32_t o3 = off + 3 * P < end ? off + 3 * P : last;
+            // The payload region has three spare entries after the last
+            // agent, so the loads past a run's end stay inside it; those
+            // slots are masked out of the test.
             const Pay q0 = *reinterpret_cast<const Pay*>(base + off);
-            const Pay q1 = *reinterpret_cast<const Pay*>(base + o1);
-            const Pay q2 = *reinterpret_cast<const Pay*>(base + o2);
-            const Pay q3 = *reinterpret_cast<const Pay*>(base + o3);
+            const Pay q1 = *reinterpret_cast<const Pay*>(base + off + P);
+            const Pay q2 = *reinterpret_cast<const Pay*>(base + off + 2 * P);
+            const Pay q3 = *reinterpret_cast<const Pay*>(base + off + 3 * P);
             test(q0, off, true);
-            test(q1, o1, off + P < end);
-            test(q2, o2, off + 2 * P < end);
-            test(q3, o3, off + 3 * P < end);
+            test(q1, off + P, off + P < end);
+            test(q2, off + 2 * P, off + 2 * P < end);
+            test(q3, off + 3 * P, off + 3 * P < end);
         }
     }
     drain();
@@ -252,11 +291,12 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 template <typename Real, typename Pay>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           uint32_t self_off, const int32_t* __restrict__ start,
+                                          const uint32_t* __restrict__ split,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
                                           uint32_t* lst, Real& fx, Real& fy, Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay>(g, c, pi, self_off, start, pay, lst, [&](uint32_t, const Pay& q) {
+    scan_contacts<Real, Pay>(g, c, pi, self_off, start, split, pay, lst, [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });
     fx = ax; fy = ay; fz = az;

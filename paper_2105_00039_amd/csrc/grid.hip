@@ -296,6 +296,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                                                  int32_t B, const SimGeom* __restrict__ geom,
                                                  const Header* __restrict__ hdr,
                                                  int32_t* __restrict__ box_id,
+                                                 uint8_t* __restrict__ quarter,
                                                  int32_t* __restrict__ hist)
 {
     using Real = typename Mode<M>::Real;
@@ -315,11 +316,13 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kTileThreads) {
         const int s = BATCHED ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
         const SimGeom& g = geom[s];
-        const int ix = axis_index((double)(Real)x[i], g.origin[0], g.edge, g.dims[0]);
+        const double px = (double)(Real)x[i];
+        const int ix = axis_index(px, g.origin[0], g.edge, g.dims[0]);
         const int iy = axis_index((double)(Real)y[i], g.origin[1], g.edge, g.dims[1]);
         const int iz = axis_index((double)(Real)z[i], g.origin[2], g.edge, g.dims[2]);
         const int key = g.box_base + ix + g.dims[0] * (iy + g.dims[1] * iz);
         box_id[i] = key;
+        quarter[i] = (uint8_t)box_quarter(px, g.origin[0], 4.0 / g.edge, g.edge, ix);
         atomicAdd(&h[key >> sb], 1);
     }
     __syncthreads();
@@ -392,6 +395,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
                                                       const typename Mode<M>::In* __restrict__ d,
                                                       int64_t n, const Header* __restrict__ hdr,
                                                       const int32_t* __restrict__ box_id,
+                                                      const uint8_t* __restrict__ quarter,
                                                       const int32_t* __restrict__ hist,
                                                       const int32_t* __restrict__ bstart,
                                                       int32_t* __restrict__ key2,
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     constexpr int G = 4;
     for (int p0 = threadIdx.x; p0 < tn; p0 += G * kTileThreads) {
         int64_t i[G];
-        int key[G];
+        int key[G], qx[G];
         typename Mode<M>::Pay q[G];
 #pragma unroll
         for (int t = 0; t < G; ++t) {
@@ -456,6 +460,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
 #pragma unroll
         for (int t = 0; t < G; ++t) {
             key[t] = box_id[i[t]];
+            qx[t] = quarter[i[t]];
             q[t].x = (Real)x[i[t]];
             q[t].y = (Real)y[i[t]];
             q[t].z = (Real)z[i[t]];
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
             const int p = p0 + t * kTileThreads;
             if (p < tn) {
                 const int pos = gcur[key[t] >> sb] + p;
-                key2[pos] = key[t];
+                key2[pos] = ((key[t] & ((1 << sb) - 1)) << 2) | qx[t];
                 idx2[pos] = (int32_t)i[t];
                 pay2[pos] = q[t];
             }
@@ -486,12 +491,14 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              const typename Mode<M>::Pay* __restrict__ pay2,
                                                              const int32_t* __restrict__ bstart,
                                                              int32_t* __restrict__ start,
+                                                             uint32_t* __restrict__ split,
                                                              int32_t* __restrict__ tmp,
                                                              int32_t* __restrict__ perm,
                                                              typename Mode<M>::Pay* __restrict__ pay)
 {
     __shared__ int32_t c[kSortBoxes];
-    __shared__ int32_t mem[kSortStage];      // input indices of each box, in arrival order
+    __shared__ int32_t mem[kSortStage];      // input index of each box member, arrival order
+    __shared__ uint8_t memq[kSortStage];     // its x-quarter
     __shared__ int32_t inv[kSortStage];      // final slot -> position in the bucket's input
     __shared__ int32_t s_wave[kSortThreads / kWave];
     if (hdr->error) return;
@@ -502,14 +509,14 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     const int b0 = b << sb;
     const int nbox = (int)((total - b0) < (1ll << sb) ? (total - b0) : (1ll << sb));
     const int s0 = bstart[b], s1 = bstart[b + 1];
-    const bool staged = (s1 - s0) <= kSortStage;
-    int32_t* members = staged ? mem : tmp + s0;   // block-uniform
+    const bool staged = (s1 - s0) <= kSortStage;   // block-uniform
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
-    for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) atomicAdd(&c[key2[e] - b0], 1);
+    for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) atomicAdd(&c[key2[e] >> 2], 1);
     __syncthreads();
-    // 2. exclusive scan of the counts -> box starts (thread t owns a contiguous chunk)
+    // 2. exclusive scan of the counts -> box starts (thread t owns a contiguous
+    //    chunk); empty boxes get their (empty) split word here
     const int per = (nbox + kSortThreads - 1) / kSortThreads;
     const int k0 = threadIdx.x * per;
     int32_t sum = 0;
@@ -520,23 +527,53 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         const int32_t v = c[k];
         c[k] = run;
         start[b0 + k] = s0 + run;
+        if (v == 0) split[b0 + k] = 0u;
         run += v;
     }
     __syncthreads();
     // 3. agents into their box range (arrival order)
     for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-        const int slot = atomicAdd(&c[key2[e] - b0], 1);
-        members[slot] = idx2[e];
+        const int kq = key2[e];
+        const int slot = atomicAdd(&c[kq >> 2], 1);
+        if (staged) {
+            mem[slot] = idx2[e];
+            memq[slot] = (uint8_t)(kq & 3);
+        } else {
+            tmp[s0 + slot] = e - s0;
+        }
     }
     __syncthreads();
-    // 4. c[k] now holds the end of box k; rank among box mates by input index
+    // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
+    //    input index); the box's first agent in that order writes the split
+    //    word (how many mates lie in quarters below 1, 2, 3).
     for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-        const int k = key2[e] - b0;
+        const int kq = key2[e];
+        const int k = kq >> 2, q = kq & 3;
         const int32_t orig = idx2[e];
         const int bs = k > 0 ? c[k - 1] : 0;
         const int be = c[k];
-        int r = 0;
-        for (int m = bs; m < be; ++m) r += (members[m] < orig) ? 1 : 0;
+        int r = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (int m = bs; m < be; ++m) {
+            int qm, im;
+            if (staged) {
+                qm = memq[m];
+                im = mem[m];
+            } else {
+                const int pm = tmp[s0 + m];
+                qm = key2[s0 + pm] & 3;
+                im = idx2[s0 + pm];
+            }
+            r += (qm < q || (qm == q && im < orig)) ? 1 : 0;
+            c1 += qm < 1 ? 1 : 0;
+            c2 += qm < 2 ? 1 : 0;
+            c3 += qm < 3 ? 1 : 0;
+        }
+        if (r == 0) {
+            const int cnt = be - bs;
+            split[b0 + k] = cnt > 255 ? kSplitNone
+                                      : (uint32_t)c1 | ((uint32_t)c2 << 8) | ((uint32_t)c3 << 16) |
+                                            ((uint32_t)cnt << 24);
+        }
         if (staged) {
             inv[bs + r] = e - s0;
         } else {
@@ -552,6 +589,30 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         perm[s0 + p] = idx2[e];
         pay[s0 + p] = pay2[e];
     }
+}
+
+// ---------------------------------------------------------- canonical order
+
+// The canonical order of the exports (ascending box, then input index) from
+// the payload order (box, quarter, input index): each payload slot ranks its
+// agent among the box's agents by input index.
+__global__ __launch_bounds__(kBlock) void k_canon(int64_t n, const Header* __restrict__ hdr,
+                                                  const int32_t* __restrict__ box_id,
+                                                  const int32_t* __restrict__ start,
+                                                  const int32_t* __restrict__ perm,
+                                                  int32_t* __restrict__ canon,
+                                                  int32_t* __restrict__ cslot)
+{
+    if (hdr->error) return;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int32_t me = perm[k];
+    const int32_t b = box_id[me];
+    const int bs = start[b], be = start[b + 1];
+    int r = 0;
+    for (int m = bs; m < be; ++m) r += perm[m] < me ? 1 : 0;
+    canon[bs + r] = me;
+    cslot[bs + r] = (int32_t)k;
 }
 
 template <int M>
@@ -581,17 +642,19 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     const unsigned nba = (unsigned)((n + kTileA - 1) / kTileA);
     if (batched)
         k_hist<M, true><<<nba, kTileThreads, 0, s>>>(x, y, z, n, woff, B, D.geom, D.hdr, D.box_id,
-                                                     D.hist);
+                                                     D.quarter, D.hist);
     else
         k_hist<M, false><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr, D.box_id,
-                                                      D.hist);
+                                                      D.quarter, D.hist);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
     k_bucketscan<<<1, 1024, 0, s>>>(D.hdr, btot, D.bstart);
-    k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.hist, D.bstart, D.key2,
+    k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter, D.hist,
+                                                D.bstart, D.key2,
                                           D.idx2, static_cast<Pay*>(D.pay2));
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
-        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), D.bstart, D.start, D.tmp, D.perm,
+        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), D.bstart, D.start, D.split, D.tmp,
+        D.perm,
         static_cast<Pay*>(D.payload));
     return hipGetLastError();
 }
@@ -602,6 +665,15 @@ hipError_t launch_init(const Layout& L, const Dev& D, hipStream_t s)
 {
     (void)L;
     k_init<<<1, 64, 0, s>>>(D.hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s)
+{
+    (void)L;
+    if (n <= 0) return hipSuccess;
+    k_canon<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, D.hdr, D.box_id, D.start,
+                                                                    D.perm, D.canon, D.cslot);
     return hipGetLastError();
 }
 

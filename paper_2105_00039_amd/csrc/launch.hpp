@@ -14,6 +14,10 @@ hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const
                              const void* z, const void* d, int64_t n, const int64_t* off,
                              int32_t B, double edge, const double* edges, hipStream_t s);
 
+// Canonical order of the last build (ascending box, then input index) into
+// D.canon / D.cslot, for the exports.
+hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s);
+
 // Forward step.  Single: p_host valid, off == nullptr.  Batched: p_dev valid.
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
