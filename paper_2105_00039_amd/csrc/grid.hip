@@ -479,6 +479,97 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     }
 }
 
+// FP32 payloads: the same partition with the permutation done in LDS.  Each
+// thread loads its own agents (coalesced), they are placed in bucket order in
+// LDS (key, tile position + quarter, payload), and each bucket run is then
+// written from LDS in order.  One block per CU (the tile needs ~120 KB).
+template <int M>
+__global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename Mode<M>::In* __restrict__ x,
+                                                                const typename Mode<M>::In* __restrict__ y,
+                                                                const typename Mode<M>::In* __restrict__ z,
+                                                                const typename Mode<M>::In* __restrict__ d,
+                                                                int64_t n, const Header* __restrict__ hdr,
+                                                                const int32_t* __restrict__ box_id,
+                                                                const uint8_t* __restrict__ quarter,
+                                                                const int32_t* __restrict__ hist,
+                                                                const int32_t* __restrict__ bstart,
+                                                                int32_t* __restrict__ key2,
+                                                                int32_t* __restrict__ idx2,
+                                                                F4* __restrict__ pay2)
+{
+    using Real = typename Mode<M>::Real;
+    static_assert(sizeof(typename Mode<M>::Pay) == sizeof(F4), "FP32 payloads only");
+    static_assert(kTileA <= 4096, "tile positions are 12-bit");
+    constexpr int IT = kTileA / kTileThreads;
+    __shared__ int32_t cnt[kBucketsMax];     // tile counts, then tile-local bucket starts
+    __shared__ int32_t gcur[kBucketsMax];    // global start of this tile's run per bucket
+    __shared__ int32_t s_key[kTileA];        // box index, bucket order
+    __shared__ uint16_t s_eq[kTileA];        // tile position | quarter << 12, bucket order
+    __shared__ F4 s_pay[kTileA];             // (x, y, z, d/2), bucket order
+    __shared__ int32_t s_wave[kTileThreads / kWave];
+    if (hdr->error) return;
+    const int sb = hdr->sb, nbk = hdr->nb;
+    for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
+    __syncthreads();
+    const unsigned tile = xcd_block();   // consecutive tiles on one XCD
+    const int64_t c0 = (int64_t)tile * kTileA;
+    const int tn = (int)((c0 + kTileA < n) ? kTileA : n - c0);
+    int key[IT], rk[IT], qx[IT];
+    F4 q[IT];
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        const int e = threadIdx.x + t * kTileThreads;
+        key[t] = -1;
+        if (e < tn) {
+            const int64_t i = c0 + e;
+            key[t] = box_id[i];
+            qx[t] = quarter[i];
+            q[t].x = (Real)x[i];
+            q[t].y = (Real)y[i];
+            q[t].z = (Real)z[i];
+            q[t].w = (Real)0.5 * (Real)d[i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < IT; ++t)
+        if (key[t] >= 0) rk[t] = atomicAdd(&cnt[key[t] >> sb], 1);
+    __syncthreads();
+    // exclusive scan of the tile counts over buckets; global run starts
+    const int per = (nbk + kTileThreads - 1) / kTileThreads;
+    const int b0 = threadIdx.x * per;
+    int32_t sum = 0;
+    for (int b = b0; b < b0 + per && b < nbk; ++b) sum += cnt[b];
+    int32_t tot;
+    int32_t run = block_excl_scan<kTileThreads, int32_t>(sum, s_wave, tot);
+    for (int b = b0; b < b0 + per && b < nbk; ++b) {
+        const int32_t v = cnt[b];
+        cnt[b] = run;
+        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + tile] - run;
+        run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < IT; ++t) {
+        if (key[t] >= 0) {
+            const int e = threadIdx.x + t * kTileThreads;
+            const int pos = cnt[key[t] >> sb] + rk[t];
+            s_key[pos] = key[t];
+            s_eq[pos] = (uint16_t)(e | (qx[t] << 12));
+            s_pay[pos] = q[t];
+        }
+    }
+    __syncthreads();
+    // bucket runs written in order: consecutive threads, consecutive addresses
+    for (int p = threadIdx.x; p < tn; p += kTileThreads) {
+        const int k = s_key[p];
+        const int eq = s_eq[p];
+        const int pos = gcur[k >> sb] + p;
+        key2[pos] = ((k & ((1 << sb) - 1)) << 2) | (eq >> 12);
+        idx2[pos] = (int32_t)(c0 + (eq & 0xfff));
+        pay2[pos] = s_pay[p];
+    }
+}
+
 // -------------------------------------------------------------- bucket sort
 
 constexpr int kSortBoxes = 1 << kSBMax;
@@ -649,9 +740,14 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
     k_bucketscan<<<1, 1024, 0, s>>>(D.hdr, btot, D.bstart);
-    k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter, D.hist,
-                                                D.bstart, D.key2,
-                                          D.idx2, static_cast<Pay*>(D.pay2));
+    if constexpr (sizeof(Pay) == sizeof(F4))
+        k_partition_lds<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
+                                                        D.hist, D.bstart, D.key2, D.idx2,
+                                                        static_cast<F4*>(D.pay2));
+    else
+        k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
+                                                    D.hist, D.bstart, D.key2, D.idx2,
+                                                    static_cast<Pay*>(D.pay2));
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
         D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), D.bstart, D.start, D.split, D.tmp,
         D.perm,
