@@ -38,9 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
                                                      int64_t n, ms_params p1,
                                                      const ms_params* __restrict__ pB,
                                                      const Header* __restrict__ hdr,
-                                                     const typename Mode<M>::Real* __restrict__ gdx,
-                                                     const typename Mode<M>::Real* __restrict__ gdy,
-                                                     const typename Mode<M>::Real* __restrict__ gdz,
+                                                     const typename Mode<M>::Pay* __restrict__ gin,
                                                      typename Mode<M>::Pay* __restrict__ fbar)
 {
     using Real = typename Mode<M>::Real;
@@ -60,8 +58,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                          (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                          fx, fy, fz);
-    const int32_t o = perm[k];
-    const Real gx = gdx[o], gy = gdy[o], gz = gdz[o];
+    const Pay gr = gin[perm[k]];
+    const Real gx = gr.x, gy = gr.y, gz = gr.z;
     const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
     Pay fb;
     fb.w = (Real)0;
@@ -87,6 +85,36 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     fbar[k] = fb;
 }
 
+// The incoming gradient packed into one record per agent (input order), so
+// k_bwd_fbar gathers one record per agent instead of three values; and the
+// outgoing gradient records split into the caller's arrays.  Both passes are
+// coalesced.
+template <typename Pay, typename Real>
+__global__ __launch_bounds__(kBlock) void k_pack3(const Real* __restrict__ a, const Real* __restrict__ b,
+                                                  const Real* __restrict__ c, int64_t n,
+                                                  const Header* __restrict__ hdr, Pay* __restrict__ out)
+{
+    if (hdr->error) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Pay v;
+    v.x = a[i]; v.y = b[i]; v.z = c[i]; v.w = (Real)0;
+    out[i] = v;
+}
+
+template <typename Pay, typename Real>
+__global__ __launch_bounds__(kBlock) void k_split4(const Pay* __restrict__ in, int64_t n,
+                                                   const Header* __restrict__ hdr, Real* __restrict__ a,
+                                                   Real* __restrict__ b, Real* __restrict__ c,
+                                                   Real* __restrict__ d)
+{
+    if (hdr->error) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Pay v = in[i];
+    a[i] = v.x; b[i] = v.y; c[i] = v.z; d[i] = v.w;
+}
+
 // Deterministic block sum: butterfly inside each wave, waves in fixed order.
 __device__ __forceinline__ double block_sum_fixed(double v, double* s_w)
 {
@@ -110,10 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
                                                        int64_t n, ms_params p1,
                                                        const ms_params* __restrict__ pB,
                                                        const Header* __restrict__ hdr,
-                                                       typename Mode<M>::Real* __restrict__ gx,
-                                                       typename Mode<M>::Real* __restrict__ gy,
-                                                       typename Mode<M>::Real* __restrict__ gz,
-                                                       typename Mode<M>::Real* __restrict__ gd,
+                                                       typename Mode<M>::Pay* __restrict__ gout,
                                                        double* __restrict__ partials)
 {
     using Real = typename Mode<M>::Real;
@@ -176,11 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             kbl += delta * eF;
             gbl -= sq * eF;
         });
-        const int32_t o = perm[k];
-        gx[o] = px;
-        gy[o] = py;
-        gz[o] = pz;
-        gd[o] = (Real)0.5 * rb;
+        Pay gr;
+        gr.x = px;
+        gr.y = py;
+        gr.z = pz;
+        gr.w = (Real)0.5 * rb;
+        gout[perm[k]] = gr;
         kb = (double)kbl;
         gb = (double)gbl;
     }
@@ -247,21 +273,25 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
     const Real *GX = (const Real*)gdx, *GY = (const Real*)gdy, *GZ = (const Real*)gdz;
     Real *OX = (Real*)gx, *OY = (Real*)gy, *OZ = (Real*)gz, *OD = (Real*)gd;
     ms_params dummy{};
+    // pay2 (free after the build) holds the packed incoming gradient, then the
+    // packed outgoing one
+    Pay* rec = static_cast<Pay*>(D.pay2);
+    k_pack3<Pay, Real><<<nb, kBlock, 0, s>>>(GX, GY, GZ, n, D.hdr, rec);
     if (batched) {
-        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
-                                                   p_dev, D.hdr, GX, GY, GZ, fb);
-        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B, n,
-                                                     dummy, p_dev, D.hdr, OX, OY, OZ, OD,
-                                                     D.partials);
+        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
+                                                   dummy, p_dev, D.hdr, rec, fb);
+        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
+                                                     n, dummy, p_dev, D.hdr, rec, D.partials);
         k_reduce_params<<<B, kBlock, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
-        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
-                                                    *p_host, nullptr, D.hdr, GX, GY, GZ, fb);
-        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr, 1,
-                                                      n, *p_host, nullptr, D.hdr, OX, OY, OZ, OD,
+        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
+                                                    n, *p_host, nullptr, D.hdr, rec, fb);
+        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
+                                                      1, n, *p_host, nullptr, D.hdr, rec,
                                                       D.partials);
         k_reduce_params<<<1, kBlock, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
     }
+    k_split4<Pay, Real><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, OX, OY, OZ, OD);
     return hipGetLastError();
 }
 

@@ -5,8 +5,8 @@
 // also give each thread one agent).  Consecutive lanes hold agents of the same
 // or neighbouring boxes, so a wavefront walks nearly the same 9 runs and its
 // candidate loads are served by L1/L2.  The force is summed in registers in
-// ascending (box, input index) order; the displacement is written to the
-// agent's input position through perm.
+// ascending (box, quarter, input index) order; the displacement is stored at
+// the agent's input position through perm (as one record, split by k_soa).
 #include "gather.hpp"
 #include "launch.hpp"
 
@@ -23,9 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
                                                   int64_t n, ms_params p1,
                                                   const ms_params* __restrict__ pB,
                                                   const Header* __restrict__ hdr,
-                                                  typename Mode<M>::Real* __restrict__ dx,
-                                                  typename Mode<M>::Real* __restrict__ dy,
-                                                  typename Mode<M>::Real* __restrict__ dz)
+                                                  typename Mode<M>::Pay* __restrict__ dout)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -47,9 +45,26 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     Real ddx, ddy, ddz;
     displacement<Real>(fx, fy, fz, (Real)P.dt, (Real)P.max_disp, (Real)P.adherence, ddx, ddy, ddz);
     const int32_t o = perm[k];
-    dx[o] = ddx;
-    dy[o] = ddy;
-    dz[o] = ddz;
+    Pay v;
+    v.x = ddx; v.y = ddy; v.z = ddz; v.w = (Real)0;
+    dout[o] = v;
+}
+
+// The force kernel stores each displacement as one 16-byte (FP64: 32-byte)
+// record at the agent's input position: one random store instead of three
+// 4-byte ones, each of which costs a whole DRAM sector.  This pass splits the
+// records into the caller's dx, dy, dz with coalesced accesses.
+template <typename Pay, typename Real>
+__global__ __launch_bounds__(kBlock) void k_soa(const Pay* __restrict__ a, int64_t n,
+                                                const Header* __restrict__ hdr,
+                                                Real* __restrict__ dx, Real* __restrict__ dy,
+                                                Real* __restrict__ dz)
+{
+    if (hdr->error) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Pay v = a[i];
+    dx[i] = v.x; dy[i] = v.y; dz[i] = v.z;
 }
 
 template <typename PT, typename DT>
@@ -219,14 +234,16 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
     Real* X = static_cast<Real*>(dx);
     Real* Y = static_cast<Real*>(dy);
     Real* Z = static_cast<Real*>(dz);
+    Pay* A = static_cast<Pay*>(D.pay2);
     if (batched) {
         ms_params dummy{};
         k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
-                                                p_dev, D.hdr, X, Y, Z);
+                                                p_dev, D.hdr, A);
     } else {
         k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
-                                                 *p_host, nullptr, D.hdr, X, Y, Z);
+                                                 *p_host, nullptr, D.hdr, A);
     }
+    k_soa<Pay, Real><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z);
     return hipGetLastError();
 }
 
