@@ -12,12 +12,14 @@ device memory before timing starts.  The timed region replays a HIP graph of
 one step K times.
 
 One JSON line is printed with, besides the headline value:
-  roofline      the force kernel's algorithmic flops per launch (9 per
-                27-box candidate + 25 per contact, the measured candidate and
-                contact counts of the workload) over its mean duration from HIP
-                events around every force launch of an eager K-step pass,
-                against the FP32 vector peak; traffic from rocprofv3 counters
-                is filled from the committed profile summary when present.
+  roofline      the force step's algorithmic flops per call (9 per 27-box
+                candidate + 25 per contact, the measured candidate and contact
+                counts of the workload) over its mean duration from HIP events
+                around every ms_mech_step call of an eager K-step pass (the
+                gather kernel k_force and the record split k_soa), against the
+                FP32 vector peak; traffic (HBM bytes of both kernels from
+                rocprofv3 counters) is filled from the committed profile summary
+                when it was taken on the current sources.
   cpu_baseline  the FP64 oracle (single thread) on the same population.
   variants      other densities / FP64, fwd+bwd and the batched workload.
 """
@@ -243,7 +245,7 @@ def force_source_hash():
 
 
 def traffic_from_profiles(workload):
-    """HBM bytes per force launch from the committed counter summary
+    """HBM bytes per ms_mech_step call from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe), if it was taken on the
     current force sources."""
     path = os.path.join(ROOT, "profiles", f"k_force_{workload}_traffic.md")
@@ -331,7 +333,8 @@ def main():
     fb = force_bytes(N, st["n_boxes"], S)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
                     frac=achieved / peak, traffic=traffic_from_profiles(f"{name}_{args.dtype}"),
-                    kernel="k_force", flops_per_agent=flops_agent, force_us=force_ms * 1e3,
+                    kernel="ms_mech_step = k_force + k_soa", flops_per_agent=flops_agent,
+                    force_us=force_ms * 1e3,
                     force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9)
     balg = bytes_alg(N, st["n_boxes"], S)
     hbm = dict(step_alg_bytes=balg, step_alg_GBps=balg * args.steps / sec / 1e9,
