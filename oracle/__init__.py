@@ -16,6 +16,8 @@ Functions and the passages they follow:
                                    displacement rule of Section III.
 * ``brute_forces``                 Eq. 1 over all pairs, no grid.
 * ``tolerance_scales``             per-agent scales of the acceptance test.
+* ``sample``                       ``step`` and ``tolerance_scales`` for a
+                                   sample of agents of a large population.
 * ``step_adjoint``                 reverse-mode derivative of ``step``.
 * ``rollout``, ``rollout_grad``    repeated steps with the grid rebuilt each
                                    step (Section IV-A) and their gradient.
@@ -80,6 +82,7 @@ def lib():
                 "orc_tolerance_scales": [I64, P, P, P, P, D, D, D, D, P, P, P],
                 "orc_step_adjoint": [I64, P, P, P, P, D, P, P, P, P, P, P, P, P, P],
                 "orc_integrate": [I64, P, P, P, P, P, P],
+                "orc_sample": [I64, P, P, P, P, D, P, D, I64, P, P, P, P, P, P, P, P, P, P],
             }
             for name, args in sig.items():
                 f = getattr(L, name)
@@ -192,6 +195,24 @@ def tolerance_scales(x, y, z, d, kappa, gamma, unit_roundoff, edge=0.0):
                                       float(gamma), float(unit_roundoff), _p(S), _p(A), _p(C)),
            "tolerance_scales")
     return S, A, C
+
+
+def sample(x, y, z, d, params, idx, unit_roundoff=0.0, edge=0.0):
+    """For the agents ``idx`` only: force F (m,3), displacement D (m,3) and the
+    acceptance scales S, A, contacts C (m,) -- the rows ``idx`` of ``step`` and
+    ``tolerance_scales`` bit for bit, with the grid built over all agents."""
+    x, y, z, d = map(_f64, (x, y, z, d))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    m = idx.size
+    F = [np.zeros(m) for _ in range(3)]
+    D = [np.zeros(m) for _ in range(3)]
+    S = np.zeros(m)
+    A = np.zeros(m)
+    C = np.zeros(m, dtype=np.int32)
+    _check(lib().orc_sample(x.size, _p(x), _p(y), _p(z), _p(d), float(edge), _p(_params(params)),
+                            float(unit_roundoff), m, _p(idx), *map(_p, F), *map(_p, D), _p(S), _p(A),
+                            _p(C)), "sample")
+    return np.stack(F, axis=1), np.stack(D, axis=1), S, A, C
 
 
 def step_adjoint(x, y, z, d, params, gD, edge=0.0):

@@ -459,6 +459,49 @@ int orc_tolerance_scales(int64_t n, const double *x, const double *y, const doub
     return ORC_OK;
 }
 
+/* ------------------------------------------------------- sampled agents --- */
+/*
+ * The same per-agent results for a sample of agents only, for checks on
+ * populations too large to evaluate whole: the grid is built over all n
+ * agents (it is cheap), then orc_step's force and displacement and
+ * orc_tolerance_scales' S, A, C are evaluated for the m agents idx[0..m) with
+ * the very same per-agent code, so row k equals row idx[k] of the full
+ * functions bit for bit.  Outputs are [m]; any output pointer may be NULL.
+ */
+int orc_sample(int64_t n, const double *x, const double *y, const double *z, const double *d,
+               double edge_in, const double *params, double u, int64_t m, const int64_t *idx,
+               double *fx, double *fy, double *fz, double *dx, double *dy, double *dz,
+               double *S, double *A, int32_t *C)
+{
+    int st = check_params(params);
+    if (st) return st;
+    for (int64_t k = 0; k < m; ++k)
+        if (idx[k] < 0 || idx[k] >= n) return ORC_EINVAL;
+    orc_grid_t G;
+    st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
+    if (st) { grid_free(&G); return st; }
+    force_ctx F = {x, y, z, d, params[0], params[1], {0, 0, 0}};
+    tol_ctx T = {x, y, z, d, params[0], params[1], u, 0, 0, 0};
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t i = idx[k];
+        F.f[0] = F.f[1] = F.f[2] = 0.0;
+        visit_candidates(&G, x, y, z, i, force_visit, &F);
+        double D[3];
+        displacement(F.f, params[2], params[3], params[4], D);
+        if (fx) { fx[k] = F.f[0]; fy[k] = F.f[1]; fz[k] = F.f[2]; }
+        if (dx) { dx[k] = D[0]; dy[k] = D[1]; dz[k] = D[2]; }
+        if (S || A || C) {
+            T.S = T.A = 0.0; T.contacts = 0;
+            visit_candidates(&G, x, y, z, i, tol_visit, &T);
+            if (S) S[k] = T.S;
+            if (A) A[k] = T.A;
+            if (C) C[k] = (int32_t)T.contacts;
+        }
+    }
+    grid_free(&G);
+    return ORC_OK;
+}
+
 /* -------------------------------------------------------------- adjoint --- */
 /*
  * Reverse-mode derivative of one step, derived from Eq. 1 and the

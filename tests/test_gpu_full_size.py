@@ -1,0 +1,226 @@
+"""GPU parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark times, on samples the oracle evaluates agent by
+agent (oracle.sample: the grid is built over every agent, the force sums only
+for the sample) and on properties that hold at any size.
+
+* clusters16M: 16,777,216 agents in 64 Gaussian clusters, FP32: grid (box of
+  every agent, box starts, canonical order) bit-exact; displacements of 4,096
+  sampled agents (random ones and members of the densest boxes) within
+  tolerance; graph-replayed steps bitwise equal to eager steps.
+* batched256: 256 simulations of 10^U(3,5) agents at 4-30 neighbours with
+  per-simulation kappa and gamma, FP32 force with FP64 positions: geometry and
+  box indices of every simulation bit-exact; 16 sampled agents per simulation
+  within tolerance of the oracle run on that simulation alone; graph replay
+  bitwise equal to eager steps.
+* adjoint262k: 262,144 agents at ~12 neighbours: one backward step against the
+  oracle's adjoint for every agent (FP64; agents of pairs within 1e-3 of
+  contact onset removed first); the 50-step rollout gradient with
+  checkpoints every 10 steps bitwise equal to checkpoints every step (FP64 and
+  FP32).
+
+Tolerances as in test_gpu_parity and test_gpu_adjoint.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2105_00039_amd as ms
+from paper_2105_00039_amd import autograd as msa
+from paper_2105_00039_amd import workloads
+from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+
+pytestmark = pytest.mark.gpu
+
+P = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ms._lib.load()
+
+
+def dev(arrs, mode):
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(NP_IN[mode]))).cuda() for a in arrs]
+
+
+def host(ts):
+    return np.stack([a.cpu().numpy().astype(np.float64) for a in ts], axis=1)
+
+
+def replay_matches_eager(step_fn, fresh, steps):
+    """Capture one step (step_fn on the tensors it is given) and replay it;
+    every replay must equal the eager trajectory bit for bit."""
+    te = fresh()
+    ref = []
+    for _ in range(steps):
+        step_fn(te)
+        ref.append([a.clone() for a in te[:3]])
+    t = fresh()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):            # warm up outside the graph
+        step_fn(fresh())
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step_fn(t)
+    for a, v in zip(t, fresh()):             # capture does not execute
+        a.copy_(v)
+    for s in range(steps):
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert torch.equal(t[k], ref[s][k]), (s, k)
+
+
+def test_full_size_clusters_16M():
+    mode = "f32"
+    pop = workloads.workload("clusters16M")
+    n = pop.n
+    arrs = pop.arrays()
+    o = oracle_inputs(arrs, mode)
+    ws = ms.Workspace(n, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t)
+    D = ms.mech_step(ws, P)
+    ms.device_status(ws)
+    g = ms.grid_get(ws)
+    box, start, perm = oracle.grid(*o)
+    assert np.array_equal(g["box_id"].cpu().numpy(), box)
+    assert np.array_equal(g["start"].cpu().numpy(), start)
+    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    rng = np.random.default_rng(16)
+    cnt = np.diff(start.astype(np.int64))
+    dense = np.argsort(cnt, kind="stable")[-64:]
+    members = np.concatenate([perm[start[b]:start[b + 1]] for b in dense]).astype(np.int64)
+    idx = np.concatenate([rng.choice(n, 3072, replace=False),
+                          rng.choice(members, min(1024, members.size), replace=False)])
+    _, Do, S, A, C = oracle.sample(*o, P, idx, UNIT[mode])
+    Dg = host(D)[idx]
+    bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+    worst = check_vectors(Dg, Do, bound, "clusters16M")
+    print(f"clusters16M: densest box {cnt.max()}, sampled contacts up to {C.max()}, "
+          f"worst err/bound {worst:.3f}")
+    del ws, t, D, g
+
+    ws2 = ms.Workspace(n, dtype=mode)
+    out = tuple(torch.empty(n, dtype=ws2.out_dtype, device="cuda") for _ in range(3))
+
+    def one(ts):
+        ms.grid_build(ws2, *ts)
+        ms.mech_step(ws2, P, out=out)
+        ms.integrate(*ts[:3], *out)
+
+    replay_matches_eager(one, lambda: dev(arrs, mode), 3)
+    ms.device_status(ws2)
+
+
+def test_full_size_batched_256():
+    mode = "f32_pos64"
+    b = workloads.workload("batched256")
+    prms = [dict(P, kappa=float(k), gamma=float(gm)) for k, gm in zip(b.kappa, b.gamma)]
+    Pd = ms.params_tensor(prms, "cuda")
+    spec = ms.BatchSpec(b.offsets)
+    ws = ms.Workspace(b.n, max_sims=b.n_sims, dtype=mode)
+    t = dev(b.arrays(), mode)
+    ms.grid_build_batched(ws, *t, spec)
+    D = ms.mech_step_batched(ws, Pd)
+    ms.device_status(ws)
+    g = ms.grid_get(ws)
+    Dg = host(D)
+    box_all = g["box_id"].cpu().numpy()
+    rng = np.random.default_rng(256)
+    worst = 0.0
+    for s in range(b.n_sims):
+        a0, a1 = int(b.offsets[s]), int(b.offsets[s + 1])
+        o = oracle_inputs(b.sim(s).arrays(), mode)
+        origin, edge, dims, nb = oracle.geometry(*o)
+        info = g["info"][s]
+        assert np.array_equal(np.array(info["origin"]), origin) and info["edge"] == edge
+        assert list(info["dims"]) == list(dims) and info["n_boxes"] == nb
+        box, _, _ = oracle.grid(*o)
+        assert np.array_equal(box_all[a0:a1] - info["box_base"], box), s
+        idx = rng.choice(a1 - a0, min(16, a1 - a0), replace=False)
+        _, Do, S, A, _ = oracle.sample(*o, prms[s], idx, UNIT[mode])
+        bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+        worst = max(worst, check_vectors(Dg[a0 + idx], Do, bound, f"batched sim {s}"))
+    print(f"batched256: {b.n} agents, worst err/bound {worst:.3f}")
+    del ws, t, D, g
+
+    ws2 = ms.Workspace(b.n, max_sims=b.n_sims, dtype=mode)
+    out = tuple(torch.empty(b.n, dtype=ws2.out_dtype, device="cuda") for _ in range(3))
+
+    def one(ts):
+        ms.grid_build_batched(ws2, *ts, spec)
+        ms.mech_step_batched(ws2, Pd, out=out)
+        ms.integrate(*ts[:3], *out)
+
+    replay_matches_eager(one, lambda: dev(b.arrays(), mode), 2)
+    ms.device_status(ws2)
+
+
+def onset_free(arrs, gap=1e-3):
+    """Drop one agent of every pair within the radius whose overlap is within
+    gap of contact onset, where d(force)/d(delta) is unbounded and the rounding
+    order of |p_i - p_j| alone would decide the last bits of the adjoint.
+    Removing agents creates no new pairs, so one pass suffices."""
+    c, _, lst = oracle.neighbors(*arrs)
+    x, y, z, d = arrs
+    i = np.repeat(np.arange(len(x)), c)
+    j = lst.astype(np.int64)
+    l = np.sqrt((x[i] - x[j]) ** 2 + (y[i] - y[j]) ** 2 + (z[i] - z[j]) ** 2)
+    near = np.abs(0.5 * d[i] + 0.5 * d[j] - l) < gap
+    keep = np.ones(len(x), dtype=bool)
+    keep[np.minimum(i[near], j[near])] = False
+    return [np.ascontiguousarray(a[keep]) for a in arrs]
+
+
+def test_full_size_adjoint_262k_step_f64():
+    mode = "f64"
+    arrs = onset_free(workloads.workload("adjoint262k").arrays())
+    pop = workloads.Population(*arrs)
+    ws = ms.Workspace(pop.n, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t)
+    rng = np.random.default_rng(262)
+    gD = rng.normal(size=(pop.n, 3))
+    gx, gy, gz, gd, gkg = ms.mech_step_backward(ws, P, *dev(gD.T, mode))
+    ms.device_status(ws)
+    gp_o, gd_o, kg_o = oracle.step_adjoint(*arrs, P, gD)
+    gp = host([gx, gy, gz])
+    assert np.abs(gp - gp_o).max() <= 1e-10 * np.abs(gp_o).max()
+    assert np.abs(gd.cpu().numpy() - gd_o).max() <= 1e-10 * np.abs(gd_o).max()
+    np.testing.assert_allclose(gkg.cpu().numpy(), kg_o, rtol=1e-9)
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+def test_full_size_adjoint_262k_rollout_checkpoints(mode):
+    """The benchmark's differentiation case: 50 steps, loss on the final
+    positions against seeded targets; checkpoints every 10 steps give the same
+    gradients, bit for bit, as checkpoints every step."""
+    pop = workloads.workload("adjoint262k")
+    tgt = workloads.targets(pop, seed=0)
+    rest = dict(dt=P["dt"], max_disp=P["max_disp"], adherence=P["adherence"])
+    ws = ms.Workspace(pop.n, dtype=mode)
+
+    def run(K):
+        t = [a.requires_grad_(True) for a in dev(pop.arrays(), mode)]
+        k = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
+        g = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        px, py, pz = msa.rollout(*t, k, g, ws, rest, 50, K)
+        tx, ty, tz = (torch.from_numpy(np.asarray(a).astype(NP_IN[mode])).cuda() for a in tgt)
+        L = ((px - tx) ** 2 + (py - ty) ** 2 + (pz - tz) ** 2).mean()
+        L.backward()
+        return L.item(), [a.grad.clone() for a in t], k.grad.item(), g.grad.item()
+
+    r10, r1 = run(10), run(1)
+    ms.device_status(ws)
+    assert r10[0] == r1[0]
+    for a, b in zip(r10[1], r1[1]):
+        assert torch.equal(a, b)
+    assert r10[2] == r1[2] and r10[3] == r1[3]
+    assert all(bool(torch.isfinite(a).all()) for a in r10[1])

@@ -306,3 +306,24 @@ def test_edge_cases():
     F1, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P)
     F2, _ = oracle.step(pop.x, pop.y, pop.z, pop.d, P, edge=30.0)
     np.testing.assert_allclose(F1, F2, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------- sampled agents ---
+
+@pytest.mark.parametrize("pop", [workloads.uniform(3000, mean_neighbors=12.0, seed=21),
+                                 workloads.clusters(2500, n_clusters=3, side=260.0, seed=22)],
+                         ids=["uniform", "clusters"])
+def test_sample_equals_full_step_rows(pop):
+    """oracle.sample (used for populations too large to evaluate whole) gives
+    exactly the rows of the full step and tolerance scales it samples."""
+    arrs = pop.arrays()
+    prm = dict(P, dt=0.05, max_disp=0.02, adherence=0.01)   # some clamped, some held
+    F, D = oracle.step(*arrs, prm)
+    S, A, C = oracle.tolerance_scales(*arrs, prm["kappa"], prm["gamma"], 2.0 ** -24)
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.integers(0, pop.n, 200), [0, pop.n - 1, 7, 7]])
+    Fs, Ds, Ss, As, Cs = oracle.sample(*arrs, prm, idx, 2.0 ** -24)
+    assert np.array_equal(Fs, F[idx]) and np.array_equal(Ds, D[idx])
+    assert np.array_equal(Ss, S[idx]) and np.array_equal(As, A[idx]) and np.array_equal(Cs, C[idx])
+    with pytest.raises(oracle.OracleError):
+        oracle.sample(*arrs, prm, np.array([pop.n]))
