@@ -17,8 +17,9 @@
 //   k_boxbase     global box range of every simulation, bucket size, error word
 //   k_hist        box index per agent (FP64 binning) and a per-block LDS
 //                 histogram over buckets (2^SB consecutive boxes)
-//   k_rowscan     per bucket: exclusive scan over blocks of its counts
-//   k_bucketscan  exclusive scan of the bucket totals
+//   k_rowscan     per bucket: exclusive scan over blocks of its counts and
+//                 the bucket's total (the partition and the bucket sort
+//                 recompute the bucket starts from the totals)
 //   k_partition   agents moved into their bucket's range (slot from an LDS
 //                 counter), carrying box index, input index and (x, y, z, d/2)
 //   k_bucketsort  one block per bucket: LDS counting sort by box, box starts,
@@ -363,26 +364,6 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(const Header* __restrict__ h
     if (threadIdx.x == 0) btot[b] = running;
 }
 
-// One block: bucket starts = exclusive scan of the bucket totals.
-__global__ __launch_bounds__(1024) void k_bucketscan(const Header* __restrict__ hdr,
-                                                     const int32_t* __restrict__ btot,
-                                                     int32_t* __restrict__ bstart)
-{
-    __shared__ int32_t s_wave[1024 / kWave];
-    if (hdr->error) return;
-    const int nbk = hdr->nb;
-    int32_t running = 0;
-    for (int c = 0; c < nbk; c += 1024) {
-        const int b = c + threadIdx.x;
-        const int32_t v = b < nbk ? btot[b] : 0;
-        int32_t tot;
-        const int32_t ex = block_excl_scan<1024, int32_t>(v, s_wave, tot);
-        if (b < nbk) bstart[b] = running + ex;
-        running += tot;
-    }
-    if (threadIdx.x == 0) bstart[nbk] = running;
-}
-
 // ---------------------------------------------------------------- partition
 
 // Each block orders its tile by bucket in LDS, then writes every bucket's run
@@ -397,7 +378,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
                                                       const int32_t* __restrict__ box_id,
                                                       const uint8_t* __restrict__ quarter,
                                                       const int32_t* __restrict__ hist,
-                                                      const int32_t* __restrict__ bstart,
+                                                      const int32_t* __restrict__ btot,
                                                       int32_t* __restrict__ key2,
                                                       int32_t* __restrict__ idx2,
                                                       typename Mode<M>::Pay* __restrict__ pay2)
@@ -429,15 +410,23 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     // exclusive scan of the tile counts over buckets; global run starts
     const int per = (nbk + kTileThreads - 1) / kTileThreads;
     const int b0 = threadIdx.x * per;
-    int32_t sum = 0;
-    for (int b = b0; b < b0 + per && b < nbk; ++b) sum += cnt[b];
-    int32_t tot;
+    // the tile's counts and the bucket totals are scanned together: the
+    // bucket starts (exclusive scan of the totals) are recomputed by every
+    // block, which is cheaper than a launch of their own
+    int32_t sum = 0, sumb = 0;
+    for (int b = b0; b < b0 + per && b < nbk; ++b) {
+        sum += cnt[b];
+        sumb += btot[b];
+    }
+    int32_t tot, totb;
     int32_t run = block_excl_scan<kTileThreads, int32_t>(sum, s_wave, tot);
+    int32_t runb = block_excl_scan<kTileThreads, int32_t>(sumb, s_wave, totb);
     for (int b = b0; b < b0 + per && b < nbk; ++b) {
         const int32_t v = cnt[b];
         cnt[b] = run;
-        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + tile] - run;
+        gcur[b] = runb + hist[(int64_t)b * gridDim.x + tile] - run;
         run += v;
+        runb += btot[b];
     }
     __syncthreads();
 #pragma unroll
@@ -492,7 +481,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
                                                                 const int32_t* __restrict__ box_id,
                                                                 const uint8_t* __restrict__ quarter,
                                                                 const int32_t* __restrict__ hist,
-                                                                const int32_t* __restrict__ bstart,
+                                                                const int32_t* __restrict__ btot,
                                                                 int32_t* __restrict__ key2,
                                                                 int32_t* __restrict__ idx2,
                                                                 F4* __restrict__ pay2)
@@ -537,15 +526,23 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
     // exclusive scan of the tile counts over buckets; global run starts
     const int per = (nbk + kTileThreads - 1) / kTileThreads;
     const int b0 = threadIdx.x * per;
-    int32_t sum = 0;
-    for (int b = b0; b < b0 + per && b < nbk; ++b) sum += cnt[b];
-    int32_t tot;
+    // the tile's counts and the bucket totals are scanned together: the
+    // bucket starts (exclusive scan of the totals) are recomputed by every
+    // block, which is cheaper than a launch of their own
+    int32_t sum = 0, sumb = 0;
+    for (int b = b0; b < b0 + per && b < nbk; ++b) {
+        sum += cnt[b];
+        sumb += btot[b];
+    }
+    int32_t tot, totb;
     int32_t run = block_excl_scan<kTileThreads, int32_t>(sum, s_wave, tot);
+    int32_t runb = block_excl_scan<kTileThreads, int32_t>(sumb, s_wave, totb);
     for (int b = b0; b < b0 + per && b < nbk; ++b) {
         const int32_t v = cnt[b];
         cnt[b] = run;
-        gcur[b] = bstart[b] + hist[(int64_t)b * gridDim.x + tile] - run;
+        gcur[b] = runb + hist[(int64_t)b * gridDim.x + tile] - run;
         run += v;
+        runb += btot[b];
     }
     __syncthreads();
 #pragma unroll
@@ -580,7 +577,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              const int32_t* __restrict__ key2,
                                                              const int32_t* __restrict__ idx2,
                                                              const typename Mode<M>::Pay* __restrict__ pay2,
-                                                             const int32_t* __restrict__ bstart,
+                                                             const int32_t* __restrict__ btot,
                                                              int32_t* __restrict__ start,
                                                              uint32_t* __restrict__ split,
                                                              int32_t* __restrict__ tmp,
@@ -599,7 +596,16 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     const int64_t total = hdr->total_boxes;
     const int b0 = b << sb;
     const int nbox = (int)((total - b0) < (1ll << sb) ? (total - b0) : (1ll << sb));
-    const int s0 = bstart[b], s1 = bstart[b + 1];
+    // bucket start: sum of the totals of the buckets before it
+    int32_t part = 0;
+    for (int k = threadIdx.x; k < b; k += kSortThreads) part += btot[k];
+    part = wave_sum<int32_t>(part);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_wave[threadIdx.x / kWave] = part;
+    __syncthreads();
+    int32_t s0 = 0;
+    for (int w = 0; w < kSortThreads / kWave; ++w) s0 += s_wave[w];
+    __syncthreads();
+    const int s1 = s0 + btot[b];
     const bool staged = (s1 - s0) <= kSortStage;   // block-uniform
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
@@ -739,17 +745,16 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
                                                       D.quarter, D.hist);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
-    k_bucketscan<<<1, 1024, 0, s>>>(D.hdr, btot, D.bstart);
     if constexpr (sizeof(Pay) == sizeof(F4))
         k_partition_lds<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
-                                                        D.hist, D.bstart, D.key2, D.idx2,
+                                                        D.hist, btot, D.key2, D.idx2,
                                                         static_cast<F4*>(D.pay2));
     else
         k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
-                                                    D.hist, D.bstart, D.key2, D.idx2,
+                                                    D.hist, btot, D.key2, D.idx2,
                                                     static_cast<Pay*>(D.pay2));
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
-        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), D.bstart, D.start, D.split, D.tmp,
+        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), btot, D.start, D.split, D.tmp,
         D.perm,
         static_cast<Pay*>(D.payload));
     return hipGetLastError();
