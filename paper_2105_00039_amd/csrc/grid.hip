@@ -174,19 +174,13 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const typename Mode<M>::In* _
 
 // ---------------------------------------------------------------- geometry
 
-// One wave per simulation (16 per block).
-__global__ __launch_bounds__(1024) void k_geometry(const BoundsPart* __restrict__ part,
-                                                   SimGeom* __restrict__ geom,
-                                                   const int64_t* __restrict__ off, int64_t n,
-                                                   int32_t B, double edge,
-                                                   const double* __restrict__ edges)
+// Geometry of the simulation holding agents [a0, a1) from its bounds partials
+// (part[c + sh] for the chunks c it overlaps); a whole wave calls it and every
+// lane gets the result.
+__device__ SimGeom geometry_of(const BoundsPart* __restrict__ part, int64_t a0, int64_t a1, int sh,
+                               double e)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int s = blockIdx.x * (1024 / kWave) + threadIdx.x / kWave;
-    if (s >= B) return;   // wave-uniform
-    const int64_t a0 = off ? off[s] : 0;
-    const int64_t a1 = off ? off[s + 1] : n;
-    const int sh = off ? s : 0;
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double dm = -INFINITY;
@@ -204,10 +198,8 @@ __global__ __launch_bounds__(1024) void k_geometry(const BoundsPart* __restrict_
     for (int k = 0; k < 3; ++k) { lo[k] = wave_min(lo[k]); hi[k] = wave_max(hi[k]); }
     dm = wave_max(dm);
     fl = wave_or(fl);
-    if (lane != 0) return;
     SimGeom g{};
     uint32_t err = fl;
-    double e = edges ? edges[s] : edge;
     if (!isfinite(e)) err |= ERR_EDGE;
     else if (e <= 0.0) e = dm;
     g.edge = e;
@@ -230,11 +222,36 @@ __global__ __launch_bounds__(1024) void k_geometry(const BoundsPart* __restrict_
     if (err) { nb = 0; g.dims[0] = g.dims[1] = g.dims[2] = 0; }
     g.error = (int32_t)err;
     g.n_boxes = nb;
-    geom[s] = g;
+    return g;
 }
 
-// One block: box base of every simulation, total boxes, bucket shift and
-// count, the error word of the build, and start[total] = n.
+// Batched builds: one wave per simulation (16 per block).
+__global__ __launch_bounds__(1024) void k_geometry(const BoundsPart* __restrict__ part,
+                                                   SimGeom* __restrict__ geom,
+                                                   const int64_t* __restrict__ off, int64_t n,
+                                                   int32_t B, double edge,
+                                                   const double* __restrict__ edges)
+{
+    const int s = blockIdx.x * (1024 / kWave) + threadIdx.x / kWave;
+    if (s >= B) return;   // wave-uniform
+    const SimGeom g = geometry_of(part, off ? off[s] : 0, off ? off[s + 1] : n, off ? s : 0,
+                                  edges ? edges[s] : edge);
+    if ((threadIdx.x & (kWave - 1)) == 0) geom[s] = g;
+}
+
+// Bucket shift (buckets of 2^sb boxes holding about kBucketAgents agents on
+// average, and no more buckets than the workspace holds) and count.
+__device__ __forceinline__ void bucket_shape(long long boxes, int64_t n, int64_t nb_cap, int& sb,
+                                             long long& nbk)
+{
+    sb = kSBMin;
+    while (sb < kSBMax && (1ll << (sb + 1)) * n <= (long long)kBucketAgents * boxes) ++sb;
+    while (sb < kSBMax && ((boxes + (1ll << sb) - 1) >> sb) > nb_cap) ++sb;
+    nbk = (boxes + (1ll << sb) - 1) >> sb;
+}
+
+// Batched builds, one block: box base of every simulation, total boxes,
+// bucket shift and count, the error word of the build, and start[total] = n.
 __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, int32_t B, int64_t n,
                                                   int64_t max_boxes, int64_t nb_cap,
                                                   int32_t* __restrict__ start)
@@ -268,12 +285,9 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         uint32_t err = s_err | hdr->off_err;
         hdr->off_err = 0u;
         if (running > max_boxes || running >= 2147483647ll) err |= ERR_CAPACITY;
-        // buckets of 2^sb boxes holding about kBucketAgents agents on average,
-        // and no more buckets than the workspace holds
-        int sb = kSBMin;
-        while (sb < kSBMax && (1ll << (sb + 1)) * n <= (long long)kBucketAgents * running) ++sb;
-        while (sb < kSBMax && ((running + (1ll << sb) - 1) >> sb) > nb_cap) ++sb;
-        const long long nbk = (running + (1ll << sb) - 1) >> sb;
+        int sb;
+        long long nbk;
+        bucket_shape(running, n, nb_cap, sb, nbk);
         if (nbk > nb_cap) err |= ERR_CAPACITY;
         hdr->need_boxes = running;
         hdr->error = err;
@@ -294,17 +308,65 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                                                  const typename Mode<M>::In* __restrict__ y,
                                                  const typename Mode<M>::In* __restrict__ z,
                                                  int64_t n, const int64_t* __restrict__ off,
-                                                 int32_t B, const SimGeom* __restrict__ geom,
-                                                 const Header* __restrict__ hdr,
+                                                 int32_t B, SimGeom* __restrict__ geom,
+                                                 Header* __restrict__ hdr,
                                                  int32_t* __restrict__ box_id,
                                                  uint8_t* __restrict__ quarter,
-                                                 int32_t* __restrict__ hist)
+                                                 int32_t* __restrict__ hist,
+                                                 const BoundsPart* __restrict__ part, double edge,
+                                                 int64_t max_boxes, int64_t nb_cap,
+                                                 int32_t* __restrict__ start)
 {
     using Real = typename Mode<M>::Real;
     __shared__ int32_t h[kBucketsMax];
     __shared__ int s_range[2];
-    if (hdr->error) return;
-    const int sb = hdr->sb, nbk = hdr->nb;
+    __shared__ SimGeom s_geo;
+    __shared__ int s_shape[3];   // sb, nb, error
+    int sb, nbk;
+    if (BATCHED) {
+        if (hdr->error) return;
+        sb = hdr->sb;
+        nbk = hdr->nb;
+    } else {
+        // One simulation: every block reduces the bounds partials itself (a
+        // launch of its own costs more), block 0 publishes the geometry and
+        // the build header for the later passes.
+        if (threadIdx.x < kWave) {
+            SimGeom g = geometry_of(part, 0, n, 0, edge);
+            if (threadIdx.x == 0) {
+                uint32_t err = (uint32_t)g.error;
+                const long long boxes = g.n_boxes;
+                if (boxes > max_boxes || boxes >= 2147483647ll) err |= ERR_CAPACITY;
+                int shift;
+                long long nb;
+                bucket_shape(boxes, n, nb_cap, shift, nb);
+                if (nb > nb_cap) err |= ERR_CAPACITY;
+                g.box_base = 0;
+                g.row_base = 0;
+                s_geo = g;
+                s_shape[0] = shift;
+                s_shape[1] = err ? 0 : (int)nb;
+                s_shape[2] = (int)err;
+                if (blockIdx.x == 0) {
+                    geom[0] = g;
+                    hdr->off_err = 0u;
+                    hdr->need_boxes = boxes;
+                    hdr->error = err;
+                    hdr->total_boxes = err ? 0 : boxes;
+                    hdr->n_agents = n;
+                    hdr->n_sims = 1u;
+                    hdr->sb = shift;
+                    hdr->nb = err ? 0 : (int32_t)nb;
+                    hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
+                    if (!err) start[boxes] = (int32_t)n;
+                }
+            }
+        }
+        __syncthreads();
+        if (s_shape[2]) return;   // block-uniform
+        sb = s_shape[0];
+        nbk = s_shape[1];
+    }
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) h[b] = 0;
     const unsigned tile = xcd_block();
     const int64_t c0 = (int64_t)tile * kTileA;
@@ -316,7 +378,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kTileThreads) {
         const int s = BATCHED ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
-        const SimGeom& g = geom[s];
+        const SimGeom& g = BATCHED ? geom[s] : s_geo;
         const double px = (double)(Real)x[i];
         const int ix = axis_index(px, g.origin[0], g.edge, g.dims[0]);
         const int iy = axis_index((double)(Real)y[i], g.origin[1], g.edge, g.dims[1]);
@@ -734,15 +796,19 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
         k_bounds<M, true><<<nbb, kBlock, 0, s>>>(x, y, z, d, n, woff, B, D.bpart);
     else
         k_bounds<M, false><<<nbb, kBlock, 0, s>>>(x, y, z, d, n, nullptr, 1, D.bpart);
-    k_geometry<<<(B + 15) / 16, 1024, 0, s>>>(D.bpart, D.geom, woff, n, B, edge, edges);
-    k_boxbase<<<1, 1024, 0, s>>>(D.hdr, D.geom, B, n, L.max_boxes, L.nb_cap, D.start);
+    if (batched) {
+        k_geometry<<<(B + 15) / 16, 1024, 0, s>>>(D.bpart, D.geom, woff, n, B, edge, edges);
+        k_boxbase<<<1, 1024, 0, s>>>(D.hdr, D.geom, B, n, L.max_boxes, L.nb_cap, D.start);
+    }
     const unsigned nba = (unsigned)((n + kTileA - 1) / kTileA);
     if (batched)
         k_hist<M, true><<<nba, kTileThreads, 0, s>>>(x, y, z, n, woff, B, D.geom, D.hdr, D.box_id,
-                                                     D.quarter, D.hist);
+                                                     D.quarter, D.hist, D.bpart, edge, L.max_boxes,
+                                                     L.nb_cap, D.start);
     else
         k_hist<M, false><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr, D.box_id,
-                                                      D.quarter, D.hist);
+                                                      D.quarter, D.hist, D.bpart, edge, L.max_boxes,
+                                                      L.nb_cap, D.start);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
     if constexpr (sizeof(Pay) == sizeof(F4))
