@@ -33,6 +33,10 @@
  *   so a sequence of them can be captured into a HIP graph.
  *   ms_mech_step* read the state copied by the last ms_grid_build* on the same
  *   workspace, so the caller may update positions in place after the build.
+ *   They also use the workspace's staging area (free after a build) for the
+ *   per-agent records they write and then split into the caller's arrays, so
+ *   two step calls on one workspace must not run concurrently even though
+ *   the workspace pointer is const.
  * Streams.  `stream` is a hipStream_t passed as void*; NULL is the null
  *   stream.  Every call is ordered on that stream.  Calls on different
  *   workspaces are independent; calls that share a workspace must be ordered.
