@@ -92,7 +92,9 @@ def contacts_per_agent(x, y, z, d, counts, lst):
 def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, backward=False):
     """Returns (seconds for `steps` steps, mean force-kernel ms or None)."""
     n = arrs[0].size
-    ws = ms.Workspace(n, dtype=dtype)
+    # The differentiated step keeps the forward's forces for the backward of
+    # the same build and parameters, as the autograd rollout does.
+    ws = ms.Workspace(n, dtype=dtype, keep_forces=backward)
     in_t = torch.float32 if dtype == "f32" else torch.float64
     t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in arrs]
     x0 = [a.clone() for a in t[:3]]

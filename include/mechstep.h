@@ -98,7 +98,8 @@ typedef struct {
 } ms_grid_info;
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
- * fields after `dtype` are updated by the grid builds.  Treat as read-only. */
+ * fields from n_agents to built are updated by the grid builds.  Treat them as
+ * read-only; keep_forces is the caller's to set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -109,6 +110,13 @@ typedef struct {
     int64_t n_agents;    /* agents of the last grid build */
     int32_t n_sims;      /* simulations of the last grid build */
     int32_t built;       /* 1 after a plain build, 2 after a batched build */
+    int32_t keep_forces; /* 0 (set by ms_workspace_init) or 1: ms_mech_step also
+                            keeps the per-agent forces (one more 4S-byte write
+                            per agent), and ms_mech_step_backward uses them
+                            instead of recomputing when the device records that
+                            they belong to the current build and the same
+                            parameters.  Results are identical either way. */
+    int32_t reserved;
 } ms_workspace;
 
 /* Bytes of device memory a workspace with these capacities needs. */

@@ -64,7 +64,7 @@ class Workspace:
     """
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
-                 dtype: str = "f32", device=None):
+                 dtype: str = "f32", device=None, keep_forces: bool = False):
         self.lib = _lib.load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -81,6 +81,18 @@ class Workspace:
         _lib.check(self.lib.ms_workspace_init(ctypes.byref(self.c), _ptr(self.buffer), int(nbytes),
                                               int(max_agents), int(max_boxes), int(max_sims),
                                               self.code, _stream(self.device)))
+        self.keep_forces = keep_forces
+        self.builds = 0   # grid builds issued on this workspace (the autograd layer checks it)
+
+    @property
+    def keep_forces(self) -> bool:
+        """Whether mech_step keeps the forces for the next mech_step_backward
+        on the same build and parameters (which then skips recomputing them)."""
+        return bool(self.c.keep_forces)
+
+    @keep_forces.setter
+    def keep_forces(self, on: bool):
+        self.c.keep_forces = 1 if on else 0
 
     @property
     def n_agents(self) -> int:
@@ -127,6 +139,7 @@ def grid_build(ws: Workspace, x, y, z, d, edge: float = 0.0):
     _check_in(ws, x, y, z, d, n=n)
     _lib.check(ws.lib.ms_grid_build(ctypes.byref(ws.c), _ptr(x), _ptr(y), _ptr(z), _ptr(d), n,
                                     float(edge), _stream(x.device)))
+    ws.builds += 1
 
 
 def _outs(ws, n, out, device):
@@ -168,6 +181,7 @@ def grid_build_batched(ws: Workspace, x, y, z, d, spec: BatchSpec):
     _lib.check(ws.lib.ms_grid_build_batched(ctypes.byref(ws.c), _ptr(x), _ptr(y), _ptr(z), _ptr(d),
                                             _ptr(spec.offsets), spec.n_sims, n, _ptr(spec.edges),
                                             _stream(x.device)))
+    ws.builds += 1
 
 
 def mech_step_batched(ws: Workspace, params_dev: torch.Tensor, out=None):

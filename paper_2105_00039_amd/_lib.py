@@ -42,7 +42,8 @@ class ms_workspace(ctypes.Structure):
                 ("max_agents", ctypes.c_int64), ("max_boxes", ctypes.c_int64),
                 ("max_sims", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("n_agents", ctypes.c_int64), ("n_sims", ctypes.c_int32),
-                ("built", ctypes.c_int32)]
+                ("built", ctypes.c_int32), ("keep_forces", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class MechStepError(RuntimeError):

@@ -43,9 +43,10 @@ class MechStep(torch.autograd.Function):
     def forward(ctx, x, y, z, d, kappa, gamma, ws: Workspace, rest: dict, edge: float = 0.0):
         p = _params(kappa, gamma, rest)
         grid_build(ws, x, y, z, d, edge)
+        ws.keep_forces = True
         D = mech_step(ws, p)
         ctx.save_for_backward(x, y, z, d)
-        ctx.ws, ctx.p, ctx.edge = ws, p, edge
+        ctx.ws, ctx.p, ctx.edge, ctx.builds = ws, p, edge, ws.builds
         ctx.kg_ref = (kappa, gamma)
         return D
 
@@ -53,7 +54,8 @@ class MechStep(torch.autograd.Function):
     def backward(ctx, gdx, gdy, gdz):
         x, y, z, d = ctx.saved_tensors
         ws = ctx.ws
-        grid_build(ws, x, y, z, d, ctx.edge)       # the workspace may have been reused
+        if ws.builds != ctx.builds:                 # the workspace was reused: rebuild
+            grid_build(ws, x, y, z, d, ctx.edge)
         g = [(t if t is not None else torch.zeros(ws.n_agents, device=ws.device))
              .to(ws.out_dtype).contiguous() for t in (gdx, gdy, gdz)]
         gx, gy, gz, gd, gkg = mech_step_backward(ws, ctx.p, *g)

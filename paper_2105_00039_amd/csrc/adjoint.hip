@@ -2,7 +2,8 @@
 // rule of Section III; the paper itself has no backward pass).
 //
 // Given g_i = dL/dDelta_i:
-//   k_bwd_fbar    recompute F_i with the forward gather and pull g_i back
+//   k_bwd_fbar    F_i (kept by the forward step of the same build and
+//                 parameters, else recomputed with the forward gather); pull g_i back
 //                 through the displacement rule:
 //                   |F| <= a : Fbar = 0
 //                   |v| <= m : Fbar = dt g
@@ -39,7 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
                                                      const ms_params* __restrict__ pB,
                                                      const Header* __restrict__ hdr,
                                                      const typename Mode<M>::Pay* __restrict__ gin,
-                                                     typename Mode<M>::Pay* __restrict__ fbar)
+                                                     typename Mode<M>::Pay* __restrict__ fbar,
+                                                     const typename Mode<M>::Pay* __restrict__ fsave)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -55,9 +57,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
-                         (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                         fx, fy, fz);
+    if (!BATCHED && kept_forces_match(hdr, p1)) {   // uniform: the forward kept F
+        const Pay f = fsave[k];
+        fx = f.x; fy = f.y; fz = f.z;
+    } else {
+        force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
+                             (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                             fx, fy, fz);
+    }
     const Pay gr = gin[perm[k]];
     const Real gx = gr.x, gy = gr.y, gz = gr.z;
     const Real dt = (Real)P.dt, m = (Real)P.max_disp, a = (Real)P.adherence;
@@ -279,13 +286,14 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
     k_pack3<Pay, Real><<<nb, kBlock, 0, s>>>(GX, GY, GZ, n, D.hdr, rec);
     if (batched) {
         k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
-                                                   dummy, p_dev, D.hdr, rec, fb);
+                                                   dummy, p_dev, D.hdr, rec, fb, nullptr);
         k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
                                                      n, dummy, p_dev, D.hdr, rec, D.partials);
         k_reduce_params<<<B, kBlock, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
         k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
-                                                    n, *p_host, nullptr, D.hdr, rec, fb);
+                                                    n, *p_host, nullptr, D.hdr, rec, fb,
+                                                    static_cast<const Pay*>(D.fsave));
         k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
                                                       D.partials);

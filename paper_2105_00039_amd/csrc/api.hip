@@ -113,6 +113,8 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->n_agents = 0;
     ws->n_sims = 0;
     ws->built = 0;
+    ws->keep_forces = 0;
+    ws->reserved = 0;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -182,7 +184,7 @@ ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, voi
     if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
-                                      dz, as_stream(stream)),
+                                      dz, ws->keep_forces != 0, as_stream(stream)),
                      who);
 }
 
@@ -198,7 +200,7 @@ ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, 
     if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
-                                      params, dx, dy, dz, as_stream(stream)),
+                                      params, dx, dy, dz, false, as_stream(stream)),
                      who);
 }
 

@@ -42,7 +42,10 @@ struct Header {
     int64_t need_boxes;    // boxes the last build asked for (even when over capacity)
     uint32_t off_err;      // simulation-offset check of the current build (cleared after use)
     int32_t total_rows;    // x-rows of boxes over all simulations of the last build
-    uint8_t pad[256 - 48];
+    uint32_t build_gen;    // incremented by every build
+    uint32_t fwd_gen;      // build_gen of the forward step that kept its forces
+    ms_params fwd_params;  // parameters of that forward step
+    uint8_t pad[256 - 96];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -79,7 +82,7 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
     size_t hdr, geom, off, bpart, box_id, quarter, start, split, hist, bstart, key2, idx2, pay2,
-        tmp, perm, payload, fbar, partials, scratch64, total;
+        tmp, perm, payload, fbar, fsave, partials, scratch64, total;
     int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
@@ -122,6 +125,7 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     // three extra entries: the gather reads up to three slots past a run's end
     L.payload = take(pay * (size_t)(na + 3));
     L.fbar = take(pay * (size_t)na);
+    L.fsave = take(pay * (size_t)na);
     L.partials = take(16 * (size_t)L.n_part);
     // int64 scratch for the neighbour-offset scan: one entry per scan tile of n+1 items
     L.scratch64 = take(8 * (size_t)((na + 1 + kScanTile - 1) / kScanTile + 1));
@@ -153,6 +157,7 @@ struct Dev {
     int32_t* cslot;
     void* payload;
     void* fbar;
+    void* fsave;        // forces of the last forward step that kept them (slot order)
     double* partials;
     long long* scratch64;
 };
@@ -180,6 +185,7 @@ inline Dev resolve(const Layout& L, void* base)
     d.cslot = d.key2;
     d.payload = b + L.payload;
     d.fbar = b + L.fbar;
+    d.fsave = b + L.fsave;
     d.partials = reinterpret_cast<double*>(b + L.partials);
     d.scratch64 = reinterpret_cast<long long*>(b + L.scratch64);
     return d;
@@ -216,6 +222,15 @@ __device__ __forceinline__ int box_quarter(double p, double o, double c4, double
     const double t = floor(((p - o) - (double)ix * e) * c4);
     const int q = (t > 0.0) ? (int)t : 0;
     return q < 3 ? q : 3;
+}
+
+// The forces kept by a forward step are those of the backward's build and
+// parameters.
+__device__ __forceinline__ bool kept_forces_match(const Header* hdr, const ms_params& p)
+{
+    const ms_params& q = hdr->fwd_params;
+    return hdr->fwd_gen == hdr->build_gen && q.kappa == p.kappa && q.gamma == p.gamma &&
+           q.dt == p.dt && q.max_disp == p.max_disp && q.adherence == p.adherence;
 }
 
 // Per-box split word: bytes 0..2 hold the number of the box's agents in

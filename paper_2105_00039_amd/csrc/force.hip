@@ -22,13 +22,20 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
                                                   const int64_t* __restrict__ off, int32_t B,
                                                   int64_t n, ms_params p1,
                                                   const ms_params* __restrict__ pB,
-                                                  const Header* __restrict__ hdr,
-                                                  typename Mode<M>::Pay* __restrict__ dout)
+                                                  Header* __restrict__ hdr,
+                                                  typename Mode<M>::Pay* __restrict__ dout,
+                                                  typename Mode<M>::Pay* __restrict__ fsave)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
     __shared__ uint32_t lst[kMaxContacts * kBlock];
     if (hdr->error) return;
+    // forces kept for the backward step: record which build and parameters
+    // they belong to (the backward uses them only on a match)
+    if (fsave && blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr->fwd_gen = hdr->build_gen;
+        hdr->fwd_params = p1;
+    }
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
@@ -42,6 +49,11 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                          (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                          fx, fy, fz);
+    if (fsave) {
+        Pay f;
+        f.x = fx; f.y = fy; f.z = fz; f.w = (Real)0;
+        fsave[k] = f;
+    }
     Real ddx, ddy, ddz;
     displacement<Real>(fx, fy, fz, (Real)P.dt, (Real)P.max_disp, (Real)P.adherence, ddx, ddy, ddz);
     const int32_t o = perm[k];
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                      void* dz, hipStream_t s)
+                      void* dz, bool keep, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -238,10 +250,11 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
     if (batched) {
         ms_params dummy{};
         k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
-                                                p_dev, D.hdr, A);
+                                                p_dev, D.hdr, A, nullptr);
     } else {
         k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
-                                                 *p_host, nullptr, D.hdr, A);
+                                                 *p_host, nullptr, D.hdr, A,
+                                                 keep ? static_cast<Pay*>(D.fsave) : nullptr);
     }
     k_soa<Pay, Real><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z);
     return hipGetLastError();
@@ -285,13 +298,13 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, hipStream_t s)
+                        void* dz, bool keep, hipStream_t s)
 {
     switch (L.dtype) {
-    case MS_F32: return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
-    case MS_F64: return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
+    case MS_F32: return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
+    case MS_F64: return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
     case MS_F32_POS64:
-        return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, s);
+        return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
     default: return hipErrorInvalidValue;
     }
 }

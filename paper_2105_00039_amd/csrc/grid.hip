@@ -297,6 +297,7 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         hdr->sb = sb;
         hdr->nb = err ? 0 : (int32_t)nbk;
         hdr->total_rows = err ? 0 : (int32_t)rows;
+        hdr->build_gen = hdr->build_gen + 1u;
         if (!err) start[running] = (int32_t)n;
     }
 }
@@ -358,6 +359,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                     hdr->sb = shift;
                     hdr->nb = err ? 0 : (int32_t)nb;
                     hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
+                    hdr->build_gen = hdr->build_gen + 1u;
                     if (!err) start[boxes] = (int32_t)n;
                 }
             }

@@ -90,3 +90,19 @@ def test_struct_layouts_match_header(tmp_path):
             _lib.ms_workspace.dtype.offset, _lib.ms_workspace.n_sims.offset,
             _lib.ms_workspace.built.offset]
     assert got == want
+
+
+def test_workspace_struct_mirror_matches_header():
+    """The ctypes mirror of ms_workspace lists the header's fields in order
+    with the same widths (the layout is part of the boundary)."""
+    from paper_2105_00039_amd import _lib
+    text = open(HEADER).read()
+    body = text[text.rindex("typedef struct {", 0, text.index("} ms_workspace;")):text.index("} ms_workspace;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    decl = re.findall(r"(void\*|size_t|int64_t|int32_t)\s+(\w+);", body)
+    width = {"void*": 8, "size_t": 8, "int64_t": 8, "int32_t": 4}
+    mirror = _lib.ms_workspace._fields_
+    assert [n for _, n in decl] == [n for n, _ in mirror]
+    for (ty, name), (_, cty) in zip(decl, mirror):
+        assert ctypes.sizeof(cty) == width[ty], name
+    assert ctypes.sizeof(_lib.ms_workspace) == sum(width[t] for t, _ in decl)

@@ -191,3 +191,35 @@ def test_rollout_gradient_central_differences_gpu_f64():
     fdg = (loss(arrs, gam=1.0 + h) - loss(arrs, gam=1.0 - h)) / (2 * h)
     assert abs(fdk - gk) <= 1e-6 * abs(gk) + 1e-9
     assert abs(fdg - gg) <= 1e-6 * abs(gg) + 1e-9
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32", "f32_pos64"])
+def test_kept_forces_give_identical_results(mode):
+    """A forward step that keeps its forces lets the backward skip the
+    recompute only for the same build and parameters; results are identical
+    bit for bit to the recomputing path, and a new build or other parameters
+    fall back to the recompute."""
+    pop = workloads.uniform(20000, mean_neighbors=12.0, seed=8)
+    n = pop.n
+    rng = np.random.default_rng(8)
+    g = dev(rng.normal(size=(3, n)), "f64" if mode == "f64" else "f32")
+    pa = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+    pb = dict(pa, kappa=2.5)
+    t = dev(pop.arrays(), mode)
+    t2 = [a + 0.3 for a in t[:3]] + [t[3]]
+    ws0 = ms.Workspace(n, dtype=mode)
+    ws1 = ms.Workspace(n, dtype=mode, keep_forces=True)
+
+    def same(u, v):
+        for a, b in zip(u, v):
+            assert torch.equal(a, b)
+
+    ms.grid_build(ws0, *t)
+    ms.grid_build(ws1, *t)
+    same(ms.mech_step(ws0, pa), ms.mech_step(ws1, pa))
+    same(ms.mech_step_backward(ws0, pa, *g), ms.mech_step_backward(ws1, pa, *g))   # kept
+    same(ms.mech_step_backward(ws0, pb, *g), ms.mech_step_backward(ws1, pb, *g))   # other params
+    ms.grid_build(ws0, *t2)
+    ms.grid_build(ws1, *t2)                                                        # new build
+    same(ms.mech_step_backward(ws0, pa, *g), ms.mech_step_backward(ws1, pa, *g))
+    ms.device_status(ws1)
