@@ -224,8 +224,8 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
 // to this lane's list in LDS (`lst`, stride kBlock) without branching (the
 // slot is always written, the cursor advances on a hit).  The pair work then
 // runs over the list, four payload loads in flight at a time.  The list is
-// drained before a group of four could overflow it, so pairs are handed over
-// in candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
+// drained (by the whole wavefront at once) before a group of four could
+// overflow any lane's list, so pairs are handed over in candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
 // payload bytes.
 template <typename Real, typename Pay, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
@@ -269,7 +269,9 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
     for (int r = 0; r < 9; ++r) {
         const uint32_t end = (uint32_t)R.e[r] * P;
         for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
-            if (cnt > kMaxContacts - 4) drain();
+            // the whole wave drains when any lane's list is nearly full: the
+            // lanes' drains run side by side instead of one after another
+            if (__any(cnt > kMaxContacts - 4)) drain();
             // The payload region has three spare entries after the last
             // agent, so the loads past a run's end stay inside it; those
             // slots are masked out of the test.

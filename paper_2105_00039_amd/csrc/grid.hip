@@ -636,6 +636,133 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
 constexpr int kSortBoxes = 1 << kSBMax;
 constexpr int kSortStage = 4096;   // buckets up to this many agents are sorted in LDS
 
+// Quarter counts of one box member, packed as the split word's bytes 0..2
+// (members in quarters below 1, 2, 3).
+__device__ __forceinline__ uint32_t split_inc(int q)
+{
+    return (q < 1 ? 1u : 0u) | (q < 2 ? 0x100u : 0u) | (q < 3 ? 0x10000u : 0u);
+}
+
+// Split word of a box of cnt agents from its packed quarter counts.
+__device__ __forceinline__ uint32_t split_word(uint32_t w, int cnt)
+{
+    return cnt > 255 ? kSplitNone : (w | ((uint32_t)cnt << 24));
+}
+
+// Buckets holding more agents than the LDS stage: after the box counts, box
+// starts and the arrival-order placement (tmp[s0 + slot] = position of the
+// slot's agent in the bucket input, c[k] = end of box k), the boxes are taken
+// in consecutive chunks of at most kSortStage agents.  Each chunk's members
+// are loaded into LDS once, ranked among their box mates by (quarter, input
+// index) there, and written in slot order; a member's box is the one whose
+// slot range holds its arrival slot.  A single box above kSortStage agents is
+// ranked straight from global memory.
+template <int M>
+__device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t* mem, uint8_t* memq,
+                            int32_t* inv, const int32_t* __restrict__ key2,
+                            const int32_t* __restrict__ idx2,
+                            const typename Mode<M>::Pay* __restrict__ pay2,
+                            const int32_t* __restrict__ tmp, uint32_t* __restrict__ split,
+                            int32_t* __restrict__ perm, typename Mode<M>::Pay* __restrict__ pay)
+{
+    int kb = 0, cs = 0;   // first box and first slot of the chunk (block-uniform)
+    while (kb < nbox) {
+        // last box of the chunk: boxes [kb, ke) end at or before cs + kSortStage
+        int lo = kb, hi = nbox;   // first box ending beyond the limit lies in [lo, hi]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (c[mid] - cs > kSortStage) hi = mid; else lo = mid + 1;
+        }
+        const int ke = lo > kb ? lo : kb + 1;
+        const int ce = c[ke - 1];
+        const int cn = ce - cs;
+        if (cn <= kSortStage) {
+            // each thread's (at most U) members: all loads issued before any use
+            constexpr int U = kSortStage / kSortThreads;
+            static_assert(U * kSortThreads == kSortStage, "whole rounds per chunk");
+            int pm[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = threadIdx.x + u * kSortThreads;
+                pm[u] = j < cn ? tmp[s0 + cs + j] : 0;
+            }
+            int32_t id[U], kq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                id[u] = idx2[s0 + pm[u]];
+                kq[u] = key2[s0 + pm[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = threadIdx.x + u * kSortThreads;
+                if (j < cn) {
+                    mem[j] = id[u];
+                    memq[j] = (uint8_t)(kq[u] & 3);
+                }
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < cn; j += kSortThreads) {
+                int k0 = kb, k1 = ke - 1;   // box of arrival slot cs + j: first with c[k] > cs + j
+                while (k0 < k1) {
+                    const int mid = (k0 + k1) >> 1;
+                    if (c[mid] > cs + j) k1 = mid; else k0 = mid + 1;
+                }
+                const int k = k0, q = memq[j];
+                const int32_t orig = mem[j];
+                const int bs = (k > 0 ? c[k - 1] : 0) - cs, be = c[k] - cs;
+                int r = 0;
+                uint32_t w = 0;
+                for (int m = bs; m < be; ++m) {
+                    const int qm = memq[m];
+                    r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
+                    w += split_inc(qm);
+                }
+                if (r == 0) split[b0 + k] = split_word(w, be - bs);
+                inv[bs + r] = j;
+            }
+            __syncthreads();
+            int jj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = threadIdx.x + u * kSortThreads;
+                jj[u] = p < cn ? inv[p] : 0;
+                pm[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
+            }
+            typename Mode<M>::Pay q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) q[u] = pay2[s0 + pm[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = threadIdx.x + u * kSortThreads;
+                if (p < cn) {
+                    perm[s0 + cs + p] = mem[jj[u]];
+                    pay[s0 + cs + p] = q[u];
+                }
+            }
+            __syncthreads();
+        } else {
+            // one box (ke = kb + 1) larger than the stage
+            const int k = kb;
+            for (int j = threadIdx.x; j < cn; j += kSortThreads) {
+                const int pe = tmp[s0 + cs + j];
+                const int q = key2[s0 + pe] & 3;
+                const int32_t orig = idx2[s0 + pe];
+                int r = 0;
+                for (int m = 0; m < cn; ++m) {
+                    const int pm = tmp[s0 + cs + m];
+                    const int qm = key2[s0 + pm] & 3;
+                    r += (qm < q || (qm == q && idx2[s0 + pm] < orig)) ? 1 : 0;
+                }
+                if (r == 0) split[b0 + k] = kSplitNone;
+                perm[s0 + cs + r] = orig;
+                pay[s0 + cs + r] = pay2[s0 + pe];
+            }
+        }
+        kb = ke;
+        cs = ce;
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __restrict__ hdr,
                                                              const int32_t* __restrict__ key2,
@@ -674,7 +801,17 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
-    for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) atomicAdd(&c[key2[e] >> 2], 1);
+    for (int e0 = s0 + threadIdx.x; e0 < s1; e0 += 4 * kSortThreads) {
+        int kq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kSortThreads;
+            kq[u] = e < s1 ? key2[e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (kq[u] >= 0) atomicAdd(&c[kq[u] >> 2], 1);
+    }
     __syncthreads();
     // 2. exclusive scan of the counts -> box starts (thread t owns a contiguous
     //    chunk); empty boxes get their (empty) split word here
@@ -693,17 +830,31 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     }
     __syncthreads();
     // 3. agents into their box range (arrival order)
-    for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-        const int kq = key2[e];
-        const int slot = atomicAdd(&c[kq >> 2], 1);
-        if (staged) {
+    if (staged) {
+        for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
+            const int kq = key2[e];
+            const int slot = atomicAdd(&c[kq >> 2], 1);
             mem[slot] = idx2[e];
             memq[slot] = (uint8_t)(kq & 3);
-        } else {
-            tmp[s0 + slot] = e - s0;
+        }
+    } else {
+        for (int e0 = s0 + threadIdx.x; e0 < s1; e0 += 4 * kSortThreads) {
+            int kq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * kSortThreads;
+                kq[u] = e < s1 ? key2[e] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (kq[u] >= 0) tmp[s0 + atomicAdd(&c[kq[u] >> 2], 1)] = e0 + u * kSortThreads - s0;
         }
     }
     __syncthreads();
+    if (!staged) {   // block-uniform
+        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, pay2, tmp, split, perm, pay);
+        return;
+    }
     // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
     //    input index); the box's first agent in that order writes the split
     //    word (how many mates lie in quarters below 1, 2, 3).
@@ -713,36 +864,16 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         const int32_t orig = idx2[e];
         const int bs = k > 0 ? c[k - 1] : 0;
         const int be = c[k];
-        int r = 0, c1 = 0, c2 = 0, c3 = 0;
+        int r = 0;
+        uint32_t w = 0;
         for (int m = bs; m < be; ++m) {
-            int qm, im;
-            if (staged) {
-                qm = memq[m];
-                im = mem[m];
-            } else {
-                const int pm = tmp[s0 + m];
-                qm = key2[s0 + pm] & 3;
-                im = idx2[s0 + pm];
-            }
-            r += (qm < q || (qm == q && im < orig)) ? 1 : 0;
-            c1 += qm < 1 ? 1 : 0;
-            c2 += qm < 2 ? 1 : 0;
-            c3 += qm < 3 ? 1 : 0;
+            const int qm = memq[m];
+            r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
+            w += split_inc(qm);
         }
-        if (r == 0) {
-            const int cnt = be - bs;
-            split[b0 + k] = cnt > 255 ? kSplitNone
-                                      : (uint32_t)c1 | ((uint32_t)c2 << 8) | ((uint32_t)c3 << 16) |
-                                            ((uint32_t)cnt << 24);
-        }
-        if (staged) {
-            inv[bs + r] = e - s0;
-        } else {
-            perm[s0 + bs + r] = orig;
-            pay[s0 + bs + r] = pay2[e];
-        }
+        if (r == 0) split[b0 + k] = split_word(w, be - bs);
+        inv[bs + r] = e - s0;
     }
-    if (!staged) return;   // block-uniform
     __syncthreads();
     // 5. write the sorted bucket in slot order
     for (int p = threadIdx.x; p < s1 - s0; p += kSortThreads) {

@@ -47,13 +47,27 @@ def _case(name):
         return t, np.zeros(999), np.zeros(999), r.uniform(8, 12, 999)
     if name == "one_box777":
         return (r.uniform(0, 6, 777), r.uniform(0, 6, 777), r.uniform(0, 6, 777), r.uniform(8, 12, 777))
+    if name == "dense_cluster30000":
+        # one tight cluster in a box-rich domain (eight far corner agents):
+        # buckets of the build above its 4096-agent LDS stage, boxes above 255
+        c = r.normal(0.0, 22.0, size=(29992, 3))
+        corners = np.array([[sx, sy, sz] for sx in (-400.0, 400.0) for sy in (-400.0, 400.0)
+                            for sz in (-400.0, 400.0)])
+        p = np.concatenate([c, corners])
+        return p[:, 0], p[:, 1], p[:, 2], r.uniform(8, 12, 30000)
+    if name == "one_box4500":
+        # a single box holding more agents than the build's LDS stage
+        return (r.uniform(0, 5, 4500), r.uniform(0, 5, 4500), r.uniform(0, 5, 4500),
+                r.uniform(8, 12, 4500))
     if name == "two":
         return np.array([0.0, 9.0]), np.zeros(2), np.zeros(2), np.array([10.0, 10.0])
     raise KeyError(name)
 
 
 CASES = ["lattice4096", "uniform10007_n12", "uniform5003_n30", "uniform3001_n4", "clusters20000",
-         "collinear999", "one_box777", "two"]
+         "collinear999", "one_box777", "dense_cluster30000", "one_box4500", "two"]
+# box capacity where the default (4 per agent + 4096) is too small
+CASE_MAX_BOXES = {"dense_cluster30000": 400_000}
 
 
 def dev(arrs, mode):
@@ -68,8 +82,8 @@ def build(arrs, mode, edge=0.0, max_boxes=None):
     return ws, t
 
 
-def step(arrs, mode, params, edge=0.0):
-    ws, t = build(arrs, mode, edge)
+def step(arrs, mode, params, edge=0.0, max_boxes=None):
+    ws, t = build(arrs, mode, edge, max_boxes)
     D = ms.mech_step(ws, params)
     ms.device_status(ws)
     return ws, np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
@@ -79,7 +93,7 @@ def step(arrs, mode, params, edge=0.0):
 @pytest.mark.parametrize("case", CASES)
 def test_grid_bit_exact(case, mode):
     arrs = _case(case)
-    ws, _ = build(arrs, mode)
+    ws, _ = build(arrs, mode, max_boxes=CASE_MAX_BOXES.get(case))
     ms.device_status(ws)
     g = ms.grid_get(ws)
     o = oracle_inputs(arrs, mode)
@@ -99,7 +113,7 @@ def test_grid_bit_exact(case, mode):
 @pytest.mark.parametrize("case", CASES)
 def test_neighbors_bit_exact(case, mode):
     arrs = _case(case)
-    ws, _ = build(arrs, mode)
+    ws, _ = build(arrs, mode, max_boxes=CASE_MAX_BOXES.get(case))
     c, off, lst = ms.neighbors(ws)
     oc, ooff, olst = oracle.neighbors(*oracle_inputs(arrs, mode))
     assert np.array_equal(c.cpu().numpy(), oc)
@@ -114,11 +128,11 @@ def test_force_and_displacement_parity(case, mode):
     o = oracle_inputs(arrs, mode)
     S, A, C = oracle.tolerance_scales(*o, 2.0, 1.0, UNIT[mode])
     # forces: with dt = 1 and no bound the displacement is the force itself
-    _, F = step(arrs, mode, P_FORCE)
+    _, F = step(arrs, mode, P_FORCE, max_boxes=CASE_MAX_BOXES.get(case))
     Fo, _ = oracle.step(*o, P_FORCE)
     check_vectors(F, Fo, force_bound(S, A, mode), f"force {case} {mode}")
     # displacements with the benchmark parameters
-    _, D = step(arrs, mode, P)
+    _, D = step(arrs, mode, P, max_boxes=CASE_MAX_BOXES.get(case))
     _, Do = oracle.step(*o, P)
     bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
     check_vectors(D, Do, bound, f"displacement {case} {mode}")
