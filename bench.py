@@ -169,6 +169,55 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     return total, force_ms, ws, t
 
 
+def time_sorted_state(ms, torch, arrs, dtype, steps, warmup, reps=10):
+    """Steps on the same population renumbered into the slot order of its
+    first build (box-sorted state, as a rollout that reorders its state
+    keeps it), and the time to reorder the four state arrays once: from the
+    random input order (first_reorder_us) and from the sorted state after one
+    step of motion (reorder_us, what a rollout pays per reorder)."""
+    n = arrs[0].size
+    in_t = torch.float32 if dtype == "f32" else torch.float64
+    ws = ms.Workspace(n, dtype=dtype)
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in arrs]
+    out = [torch.empty_like(a) for a in t]
+
+    def reorder_us():
+        for a, o in zip(t, out):
+            ms.reorder(ws, a, out=o)
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a0.record()
+        for _ in range(reps):
+            for a, o in zip(t, out):
+                ms.reorder(ws, a, out=o)
+        a1.record()
+        torch.cuda.synchronize()
+        ms.device_status(ws)
+        return a0.elapsed_time(a1) / reps * 1e3
+
+    ms.grid_build(ws, *t)
+    first_us = reorder_us()
+    sarrs = [o.cpu().numpy() for o in out]
+    # one step of motion on the sorted state, then the reorder a rollout does
+    for a, o in zip(t, out):
+        a.copy_(o)
+    disp = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+    ms.grid_build(ws, *t)
+    ms.mech_step(ws, PARAMS, out=disp)
+    ms.integrate(*t[:3], *disp)
+    ms.grid_build(ws, *t)
+    steady_us = reorder_us()
+    del ws, t, out, disp
+    sec, _, _, _ = time_plain(ms, torch, sarrs, dtype, steps, warmup, graph=True)
+    return dict(value=n * steps / sec, unit="agent-steps/s", ms_per_step=sec / steps * 1e3,
+                reorder_us=steady_us, first_reorder_us=first_us,
+                what="graph-replayed steps on the box-sorted state (ms_reorder of x, y, z, d "
+                     "into the slot order of the first build); reorder_us: one reorder of the "
+                     "four arrays of a sorted state after a step of motion; first_reorder_us: "
+                     "the same from the random input order")
+
+
 def time_batched(ms, torch, steps, warmup, seed=0):
     from paper_2105_00039_amd import workloads
     b = workloads.batched(seed=seed)
@@ -355,14 +404,25 @@ def main():
             a2 = [a.astype(np_in) for a in p2.arrays()]
             s3, _, _, _ = time_plain(ms, torch, a2, args.dtype, args.steps, args.warmup, graph=True)
             extras[f"plain_{args.dtype}_n{nb:g}"] = N * args.steps / s3
+        # clustered workload: 16,777,216 agents in 64 Gaussian clusters, FP32
+        cl = workloads.workload("clusters16M", seed=args.seed)
+        carrs = [a.astype(np.float32) for a in cl.arrays()]
+        del cl
+        s5, _, _, _ = time_plain(ms, torch, carrs, "f32", args.steps, args.warmup, graph=True)
+        extras["clusters16M_f32"] = carrs[0].size * args.steps / s5
+        extras["clusters16M_f32_ms_per_step"] = s5 / args.steps * 1e3
+        del carrs
+        torch.cuda.empty_cache()
+        sorted_state = time_sorted_state(ms, torch, arrs, args.dtype, args.steps, args.warmup)
         s4, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
                                  backward=True)
         fwd_bwd = dict(value=N * args.steps / s4, unit="agent-steps/s", ms_per_step=s4 / args.steps * 1e3,
                        what="grid build + forward + backward + integrate, same workload")
         batched = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup)
-        log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; batched {batched['value']:.3e}")
+        log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; batched {batched['value']:.3e}; "
+            f"sorted state {sorted_state['value']:.3e} (reorder {sorted_state['reorder_us']:.1f} us)")
     else:
-        fwd_bwd = batched = None
+        fwd_bwd = batched = sorted_state = None
 
     cpu = None
     if not args.no_cpu:
@@ -379,7 +439,7 @@ def main():
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
-        "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched,
+        "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched, "sorted_state": sorted_state,
     }
     print(json.dumps(rec), flush=True)
 

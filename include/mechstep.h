@@ -189,6 +189,22 @@ ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params*
 ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                        const void* dz, int64_t n, ms_dtype dtype, void* stream);
 
+/* Sorted-state rollouts (the agent sorting of Section IV-D, kept across
+ * steps): dst[k] = src[perm[k]] for the n_agents slots of the last build, where
+ * perm is the workspace's slot order: ascending box, then x-quarter of the
+ * agent inside its box, then input index.  (ms_grid_get's perm is the
+ * canonical order, ascending box then input index; both are box-sorted.)
+ * Applying it to every per-agent array of the caller (positions, diameters and
+ * any attributes) renumbers the agents in box order, so the next build reads
+ * nearly sorted input and writes the displacements nearly in order; agents of
+ * one simulation of a batched build stay inside that simulation's range.
+ * src, dst: device arrays of n_agents elements of elem_bytes (1, 2, 4, 8 or
+ * 16) bytes, aligned to elem_bytes; they must not overlap (MS_EINVAL).  The
+ * caller owns both.  A device error of the last build leaves dst unwritten.
+ * Stream-ordered; allocates nothing. */
+ms_status ms_reorder(const ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
+                     void* stream);
+
 /* Copy out the last build (synchronises `stream`).  info: host array with
  * one entry per simulation (n_sims of the build).  box_id [n] (global box of
  * each agent, caller order), box_start [total boxes + 1] (first sorted slot

@@ -24,7 +24,8 @@ from ._lib import MechStepError, MS_F32, MS_F64, MS_F32_POS64  # noqa: F401
 __all__ = [
     "Workspace", "BatchSpec", "grid_build", "mech_step", "mech_step_backward",
     "grid_build_batched", "mech_step_batched", "mech_step_backward_batched", "integrate",
-    "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError", "params_tensor",
+    "reorder", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
+    "params_tensor",
 ]
 
 _DTYPES = {
@@ -228,6 +229,23 @@ def integrate(x, y, z, dx, dy, dz):
             raise ValueError("integrate: contiguous device tensors of equal length required")
     _lib.check(lib.ms_integrate(_ptr(x), _ptr(y), _ptr(z), _ptr(dx), _ptr(dy), _ptr(dz), n, code,
                                 _stream(x.device)))
+
+
+def reorder(ws: Workspace, src, out=None):
+    """out[k] = src[perm[k]]: a per-agent device tensor (1, 2, 4, 8 or
+    16-byte elements) into the slot order of the last build (ascending box,
+    x-quarter inside the box, input index).  Applied to every per-agent array
+    it keeps a rollout's state box-sorted (ms_reorder)."""
+    n = ws.n_agents
+    if ws.c.built and (src.numel() != n or not src.is_contiguous() or src.device.type != "cuda"):
+        raise ValueError("reorder: a contiguous device tensor of n_agents elements is required")
+    if out is None:
+        out = torch.empty_like(src)
+    elif out.numel() != src.numel() or out.dtype != src.dtype or not out.is_contiguous():
+        raise ValueError("reorder: out must match src")
+    _lib.check(ws.lib.ms_reorder(ctypes.byref(ws.c), _ptr(src), _ptr(out), src.element_size(),
+                                 _stream(ws.device)))
+    return out
 
 
 def grid_get(ws: Workspace):

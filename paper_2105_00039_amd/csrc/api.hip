@@ -257,6 +257,27 @@ ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy
     return check_hip(ms::launch_integrate(x, y, z, dx, dy, dz, n, dtype, as_stream(stream)), who);
 }
 
+ms_status ms_reorder(const ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
+                     void* stream)
+{
+    const char* who = "ms_reorder";
+    ms_status st = check_ws(ws, who);
+    if (st) return st;
+    if (!ws->built) return fail(MS_EINVAL, "%s: no grid build", who);
+    if (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8 && elem_bytes != 16)
+        return fail(MS_EINVAL, "%s: elem_bytes must be 1, 2, 4, 8 or 16", who);
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    if ((st = check_arrays(who, (size_t)elem_bytes, {src, dst}))) return st;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    const uintptr_t len = (uintptr_t)n * (uintptr_t)elem_bytes;
+    if (a < b + len && b < a + len) return fail(MS_EINVAL, "%s: src and dst overlap", who);
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_reorder(ms::resolve(L, ws->base), n, src, dst, elem_bytes,
+                                        as_stream(stream)),
+                     who);
+}
+
 ms_status ms_grid_get(const ms_workspace* ws, ms_grid_info* info, int32_t* box_id,
                       int32_t* box_start, int32_t* perm, void* stream)
 {

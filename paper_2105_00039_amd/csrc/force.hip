@@ -309,6 +309,33 @@ hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
     }
 }
 
+// dst[k] = src[perm[k]]: any per-agent array into the slot order of the
+// last build.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reorder(const int32_t* __restrict__ perm,
+                                                    const T* __restrict__ src, T* __restrict__ dst,
+                                                    int64_t n, const Header* __restrict__ hdr)
+{
+    if (hdr->error) return;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) dst[k] = src[perm[k]];
+}
+
+hipError_t launch_reorder(const Dev& D, int64_t n, const void* src, void* dst, int elem_bytes,
+                          hipStream_t s)
+{
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    switch (elem_bytes) {
+    case 1: k_reorder<uint8_t><<<nb, kBlock, 0, s>>>(D.perm, (const uint8_t*)src, (uint8_t*)dst, n, D.hdr); break;
+    case 2: k_reorder<uint16_t><<<nb, kBlock, 0, s>>>(D.perm, (const uint16_t*)src, (uint16_t*)dst, n, D.hdr); break;
+    case 4: k_reorder<uint32_t><<<nb, kBlock, 0, s>>>(D.perm, (const uint32_t*)src, (uint32_t*)dst, n, D.hdr); break;
+    case 8: k_reorder<uint2><<<nb, kBlock, 0, s>>>(D.perm, (const uint2*)src, (uint2*)dst, n, D.hdr); break;
+    case 16: k_reorder<uint4><<<nb, kBlock, 0, s>>>(D.perm, (const uint4*)src, (uint4*)dst, n, D.hdr); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                             const void* dz, int64_t n, int dtype, hipStream_t s)
 {

@@ -32,6 +32,11 @@ hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, 
 hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                             const void* dz, int64_t n, int dtype, hipStream_t s);
 
+// dst[k] = src[perm[k]] for the n slots of the last build (elem_bytes 1, 2, 4,
+// 8 or 16).
+hipError_t launch_reorder(const Dev& D, int64_t n, const void* src, void* dst, int elem_bytes,
+                          hipStream_t s);
+
 // Neighbour export: counts + offsets (phase 1), list (phase 2).
 hipError_t launch_neighbors_count(const Layout& L, const Dev& D, int64_t n, int32_t B,
                                   bool batched, int32_t* counts, int64_t* offsets, hipStream_t s);
