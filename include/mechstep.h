@@ -177,6 +177,24 @@ ms_status ms_grid_build_batched(ms_workspace* ws, const void* x, const void* y, 
 ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, void* dx,
                                void* dy, void* dz, void* stream);
 
+/* One rollout step after the build: ms_mech_step followed by ms_integrate in
+ * fewer passes.  The displacement of every agent (Section III) is added to
+ * the positions x, y, z in place (the caller's order; MS_F32 positions are
+ * float, MS_F64 and MS_F32_POS64 double, with the displacement converted as
+ * ms_integrate converts it), bit for bit as the two separate calls.  dx, dy,
+ * dz: all NULL, or all given to also receive the displacements.  x, y, z
+ * need not be the build's inputs (the build keeps its own copy) but must not
+ * overlap dx, dy, dz.  On a device error of the build nothing moves.
+ * Stream-ordered; allocates nothing. */
+ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* params, void* x, void* y,
+                                 void* z, void* dx, void* dy, void* dz, void* stream);
+
+/* The same for every simulation of the last batched build; params: device
+ * ms_params [B] as for ms_mech_step_batched. */
+ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params* params, void* x,
+                                         void* y, void* z, void* dx, void* dy, void* dz,
+                                         void* stream);
+
 /* ms_mech_step_backward per simulation; g_params: device double [2B]. */
 ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
                                         const void* gdx, const void* gdy, const void* gdz,

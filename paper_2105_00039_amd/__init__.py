@@ -24,6 +24,7 @@ from ._lib import MechStepError, MS_F32, MS_F64, MS_F32_POS64  # noqa: F401
 __all__ = [
     "Workspace", "BatchSpec", "grid_build", "mech_step", "mech_step_backward",
     "grid_build_batched", "mech_step_batched", "mech_step_backward_batched", "integrate",
+    "mech_step_integrate", "mech_step_batched_integrate",
     "reorder", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
     "params_tensor",
 ]
@@ -160,6 +161,19 @@ def mech_step(ws: Workspace, params, out=None):
     return dx, dy, dz
 
 
+def mech_step_integrate(ws: Workspace, params, x, y, z, out=None):
+    """One rollout step on the last plain build: the displacements are added
+    to the positions x, y, z in place (bitwise as mech_step then integrate);
+    out, when given, also receives (dx, dy, dz)."""
+    n = ws.n_agents
+    _check_in(ws, x, y, z, n=n)
+    d = (None, None, None) if out is None else _outs(ws, n, out, ws.device)
+    p = _params(params)
+    _lib.check(ws.lib.ms_mech_step_integrate(ctypes.byref(ws.c), ctypes.byref(p), _ptr(x), _ptr(y),
+                                             _ptr(z), *(_ptr(a) for a in d), _stream(ws.device)))
+    return out
+
+
 def mech_step_backward(ws: Workspace, params, gdx, gdy, gdz, out=None, g_params=None):
     """(gx, gy, gz, gd, g_params[2]) = pullback of dL/dDelta through one step."""
     n = ws.n_agents
@@ -196,6 +210,21 @@ def mech_step_batched(ws: Workspace, params_dev: torch.Tensor, out=None):
     _lib.check(ws.lib.ms_mech_step_batched(ctypes.byref(ws.c), _ptr(params_dev), _ptr(dx), _ptr(dy),
                                            _ptr(dz), _stream(ws.device)))
     return dx, dy, dz
+
+
+def mech_step_batched_integrate(ws: Workspace, params_dev: torch.Tensor, x, y, z, out=None):
+    """mech_step_integrate for every simulation of the last batched build."""
+    n = ws.n_agents
+    if params_dev.dtype != torch.float64 or params_dev.device.type != "cuda" or not params_dev.is_contiguous():
+        raise TypeError("params must be a contiguous float64 device tensor [B, 5]")
+    if params_dev.shape != (ws.n_sims, 5):
+        raise ValueError(f"params must have shape ({ws.n_sims}, 5)")
+    _check_in(ws, x, y, z, n=n)
+    d = (None, None, None) if out is None else _outs(ws, n, out, ws.device)
+    _lib.check(ws.lib.ms_mech_step_batched_integrate(
+        ctypes.byref(ws.c), _ptr(params_dev), _ptr(x), _ptr(y), _ptr(z), *(_ptr(a) for a in d),
+        _stream(ws.device)))
+    return out
 
 
 def mech_step_backward_batched(ws: Workspace, params_dev, gdx, gdy, gdz, out=None, g_params=None):

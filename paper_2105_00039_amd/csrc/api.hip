@@ -184,7 +184,37 @@ ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, voi
     if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
-                                      dz, ws->keep_forces != 0, as_stream(stream)),
+                                      dz, nullptr, nullptr, nullptr, ws->keep_forces != 0,
+                                      as_stream(stream)),
+                     who);
+}
+
+// Arguments of the fused step + position update: positions required, the
+// displacement arrays all present or all null.
+static ms_status check_step_integrate(const ms_workspace* ws, void* x, void* y, void* z, void* dx,
+                                      void* dy, void* dz, const char* who)
+{
+    ms_status st = check_arrays(who, in_size(ws->dtype), {x, y, z});
+    if (st) return st;
+    const int nd = (dx != nullptr) + (dy != nullptr) + (dz != nullptr);
+    if (nd != 0 && nd != 3) return fail(MS_EINVAL, "%s: dx, dy, dz must all be given or all NULL", who);
+    if (nd == 3) return check_arrays(who, out_size(ws->dtype), {dx, dy, dz});
+    return MS_OK;
+}
+
+ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, void* x, void* y,
+                                 void* z, void* dx, void* dy, void* dz, void* stream)
+{
+    const char* who = "ms_mech_step_integrate";
+    ms_status st = step_common(ws, 1, who);
+    if (st) return st;
+    if ((st = check_params(p, who))) return st;
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    if ((st = check_step_integrate(ws, x, y, z, dx, dy, dz, who))) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
+                                      dz, x, y, z, ws->keep_forces != 0, as_stream(stream)),
                      who);
 }
 
@@ -200,7 +230,25 @@ ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, 
     if ((st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
-                                      params, dx, dy, dz, false, as_stream(stream)),
+                                      params, dx, dy, dz, nullptr, nullptr, nullptr, false,
+                                      as_stream(stream)),
+                     who);
+}
+
+ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params* params, void* x,
+                                         void* y, void* z, void* dx, void* dy, void* dz,
+                                         void* stream)
+{
+    const char* who = "ms_mech_step_batched_integrate";
+    ms_status st = step_common(ws, 2, who);
+    if (st) return st;
+    if (!params || !aligned(params, 8)) return fail(MS_EINVAL, "%s: null or misaligned params", who);
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    if ((st = check_step_integrate(ws, x, y, z, dx, dy, dz, who))) return st;
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
+                                      params, dx, dy, dz, x, y, z, false, as_stream(stream)),
                      who);
 }
 

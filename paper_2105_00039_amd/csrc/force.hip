@@ -79,6 +79,27 @@ __global__ __launch_bounds__(kBlock) void k_soa(const Pay* __restrict__ a, int64
     dx[i] = v.x; dy[i] = v.y; dz[i] = v.z;
 }
 
+// k_soa fused with the position update of a rollout: p += Delta in place
+// (p in the caller's order, Delta converted as k_integrate converts it), and
+// Delta itself written when dx is non-null.  Nothing moves after a device
+// error.
+template <typename Pay, typename Real, typename PT>
+__global__ __launch_bounds__(kBlock) void k_soa_integrate(const Pay* __restrict__ a, int64_t n,
+                                                          const Header* __restrict__ hdr,
+                                                          Real* __restrict__ dx, Real* __restrict__ dy,
+                                                          Real* __restrict__ dz, PT* __restrict__ x,
+                                                          PT* __restrict__ y, PT* __restrict__ z)
+{
+    if (hdr->error) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Pay v = a[i];
+    if (dx) { dx[i] = v.x; dy[i] = v.y; dz[i] = v.z; }
+    x[i] += (PT)v.x;
+    y[i] += (PT)v.y;
+    z[i] += (PT)v.z;
+}
+
 template <typename PT, typename DT>
 __global__ __launch_bounds__(kBlock) void k_integrate(PT* __restrict__ x, PT* __restrict__ y,
                                                       PT* __restrict__ z,
@@ -237,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                      void* dz, bool keep, hipStream_t s)
+                      void* dz, void* px, void* py, void* pz, bool keep, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -256,7 +277,14 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
                                                  *p_host, nullptr, D.hdr, A,
                                                  keep ? static_cast<Pay*>(D.fsave) : nullptr);
     }
-    k_soa<Pay, Real><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z);
+    if (px) {
+        using In = typename Mode<M>::In;
+        k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),
+                                                             static_cast<In*>(py),
+                                                             static_cast<In*>(pz));
+    } else {
+        k_soa<Pay, Real><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z);
+    }
     return hipGetLastError();
 }
 
@@ -298,13 +326,16 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, bool keep, hipStream_t s)
+                        void* dz, void* px, void* py, void* pz, bool keep, hipStream_t s)
 {
     switch (L.dtype) {
-    case MS_F32: return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
-    case MS_F64: return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
+    case MS_F32:
+        return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep, s);
+    case MS_F64:
+        return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep, s);
     case MS_F32_POS64:
-        return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, keep, s);
+        return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz,
+                                        keep, s);
     default: return hipErrorInvalidValue;
     }
 }
