@@ -331,6 +331,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the eager K-step pass (for rocprofv3 runs)")
+    ap.add_argument("--workload", default="uniform2M", choices=["uniform2M", "clusters16M"],
+                    help="with --profile-only: the population of the eager pass (clusters16M: "
+                         "16,777,216 agents in 64 Gaussian clusters, FP32)")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="with --profile-only: also run the copy probe once on MIB MiB "
                          "(the known-size kernel that scales rocprofv3 byte counters)")
@@ -356,6 +359,12 @@ def main():
     log(f"workload {name} {args.dtype}: {N} agents, cube side {pop.meta['side']:.1f}")
 
     if args.profile_only:
+        if args.workload == "clusters16M":
+            del pop, arrs
+            cl = workloads.workload("clusters16M", seed=args.seed)
+            arrs = [a.astype(np.float32) for a in cl.arrays()]
+            args.dtype = "f32"
+            log(f"workload clusters16M f32: {arrs[0].size} agents")
         sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
         log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
         if args.probe_copy:
