@@ -298,11 +298,10 @@ def force_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload):
-    """HBM bytes per ms_mech_step call from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe), if it was taken on the
-    current force sources."""
-    path = os.path.join(ROOT, "profiles", f"k_force_{workload}_traffic.md")
+def profile_values(name):
+    """The `- key: value` lines of a committed profile summary, or None when
+    the summary is missing or was taken on other force sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -313,8 +312,30 @@ def traffic_from_profiles(workload):
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("force_source_hash") != force_source_hash():
         return None
+    return vals
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per ms_mech_step call from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy probe), if it was taken on the
+    current force sources."""
+    vals = profile_values(f"k_force_{workload}_traffic.md")
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
+    except (KeyError, ValueError):
+        return None
+
+
+def issue_from_profiles(workload):
+    """Issue-side utilisation of the force kernel from the committed counter
+    summary (VALU issue share of the SIMD cycles, texture address/data unit
+    busy), if it was taken on the current force sources."""
+    vals = profile_values(f"k_force_{workload}_counters.md")
+    if not vals:
+        return None
+    try:
+        return {k: float(vals[k]) for k in ("valu_issue_frac", "ta_busy_frac", "td_busy_frac",
+                                            "valu_insts_per_wave")}
     except (KeyError, ValueError):
         return None
 
@@ -398,7 +419,8 @@ def main():
                     frac=achieved / peak, traffic=traffic_from_profiles(f"{name}_{args.dtype}"),
                     kernel="ms_mech_step = k_force + k_soa (the timed rollout step runs k_soa_integrate)", flops_per_agent=flops_agent,
                     force_us=force_ms * 1e3,
-                    force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9)
+                    force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9,
+                    issue=issue_from_profiles(f"{name}_{args.dtype}"))
     balg = bytes_alg(N, st["n_boxes"], S)
     hbm = dict(step_alg_bytes=balg, step_alg_GBps=balg * args.steps / sec / 1e9,
                frac_of_peak=balg * args.steps / sec / HBM_PEAK)
