@@ -222,6 +222,105 @@ def time_sorted_state(ms, torch, arrs, dtype, steps, warmup, reps=10):
                      "the same from the random input order")
 
 
+def time_host_state(ms, torch, arrs, steps, warmup):
+    """Host co-processing: the state (x, y, z, d) lives in pinned host memory,
+    as in the paper's deployment, and every step copies it to the GPU, builds
+    the grid, steps and integrates there, and copies the positions back.
+    (a) one simulation, copies and compute in sequence; (b) the population
+    split into two independent simulations on two streams of default priority,
+    so one's copies overlap the other's compute.  Rates count all agents."""
+    n = arrs[0].size
+    host = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in arrs]
+
+    def sim(lo, hi):
+        m = hi - lo
+        ws = ms.Workspace(m, dtype="f32")
+        dev = [torch.empty(m, dtype=torch.float32, device="cuda") for _ in range(4)]
+        return ws, dev, [h[lo:hi] for h in host]
+
+    def one(ws, dev, hs):
+        for dv, h in zip(dev, hs):
+            dv.copy_(h, non_blocking=True)
+        ms.grid_build(ws, *dev)
+        ms.mech_step_integrate(ws, PARAMS, *dev[:3])
+        for dv, h in zip(dev[:3], hs[:3]):
+            h.copy_(dv, non_blocking=True)
+
+    def run(sims, streams, k):
+        for _ in range(k):
+            for sm, st in zip(sims, streams):
+                with torch.cuda.stream(st):
+                    one(*sm)
+        torch.cuda.synchronize()
+
+    out = {}
+    for label, sims in (("one_sim", [sim(0, n)]), ("two_sims_overlapped", [sim(0, n // 2), sim(n // 2, n)])):
+        streams = [torch.cuda.Stream() for _ in sims]
+        run(sims, streams, warmup)
+        t0 = time.perf_counter()
+        run(sims, streams, steps)
+        sec = time.perf_counter() - t0
+        for ws, _, _ in sims:
+            ms.device_status(ws)
+        out[label] = n * steps / sec
+        out[label + "_ms_per_step"] = sec / steps * 1e3
+        del sims
+    out.update(unit="agent-steps/s", bytes_per_step=n * 16 + n * 12,
+               what="pinned host state (x, y, z, d) copied in and positions copied out every "
+                    "step around build + step + integrate; PCIe-inclusive, host-clock timed")
+    return out
+
+
+def time_growing(ms, torch, steps, seed=0, n0=1_048_576, growth=1.04):
+    """Variable population: a 1,048,576-agent uniform population (n≈12) grows by
+    the synthetic division rule of workloads.grow_and_divide (done here on the
+    device with torch ops: d *= growth, agents above 12 split into two
+    half-volume daughters) and is stepped on one workspace sized for the final
+    count.  Timed with events: grid build + step + integrate of every step;
+    the rate is sum(N_t) / sum(time_t)."""
+    from paper_2105_00039_amd import workloads
+    pop = workloads.uniform(n0, mean_neighbors=12.0, seed=seed)
+    t = [torch.from_numpy(a.astype(np.float32)).cuda() for a in pop.arrays()]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 77)
+    ws = ms.Workspace(4 * n0, dtype="f32")
+    ev = []
+    sizes = []
+    for _ in range(steps):
+        x, y, z, d = t
+        d = d * growth
+        div = torch.nonzero(d > 12.0).squeeze(1)
+        if div.numel():
+            u = torch.randn(div.numel(), 3, device="cuda", generator=gen, dtype=torch.float32)
+            u = u / u.norm(dim=1, keepdim=True)
+            off = (d[div] / 4.0)[:, None] * u
+            dd = d[div] / 2.0 ** (1.0 / 3.0)
+            px, py, pz = x[div], y[div], z[div]
+            x = x.clone(); y = y.clone(); z = z.clone()
+            x[div] = px + off[:, 0]; y[div] = py + off[:, 1]; z[div] = pz + off[:, 2]; d[div] = dd
+            x = torch.cat([x, px - off[:, 0]]); y = torch.cat([y, py - off[:, 1]])
+            z = torch.cat([z, pz - off[:, 2]]); d = torch.cat([d, dd])
+        t = [x.contiguous(), y.contiguous(), z.contiguous(), d.contiguous()]
+        if t[0].numel() > 4 * n0:
+            break
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ms.grid_build(ws, *t)
+        ms.mech_step_integrate(ws, PARAMS, *t[:3])
+        e1.record()
+        ev.append((e0, e1))
+        sizes.append(t[0].numel())
+    torch.cuda.synchronize()
+    ms.device_status(ws)
+    times = [a.elapsed_time(b) / 1e3 for a, b in ev]
+    return dict(value=sum(sizes) / sum(times), unit="agent-steps/s", steps=len(sizes),
+                n_first=sizes[0], n_last=sizes[-1], ms_per_step_first=times[0] * 1e3,
+                ms_per_step_last=times[-1] * 1e3,
+                what="growing population (synthetic division rule), eager build + fused step "
+                     "per step on one workspace, events around each step")
+
+
 def time_batched(ms, torch, steps, warmup, seed=0):
     from paper_2105_00039_amd import workloads
     b = workloads.batched(seed=seed)
@@ -448,15 +547,19 @@ def main():
         del carrs
         torch.cuda.empty_cache()
         sorted_state = time_sorted_state(ms, torch, arrs, args.dtype, args.steps, args.warmup)
+        host_state = time_host_state(ms, torch, arrs, args.steps, args.warmup) \
+            if args.dtype == "f32" else None
+        growing = time_growing(ms, torch, args.steps, seed=args.seed)
         s4, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
                                  backward=True)
         fwd_bwd = dict(value=N * args.steps / s4, unit="agent-steps/s", ms_per_step=s4 / args.steps * 1e3,
                        what="grid build + forward + backward + integrate, same workload")
         batched = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup)
         log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; batched {batched['value']:.3e}; "
-            f"sorted state {sorted_state['value']:.3e} (reorder {sorted_state['reorder_us']:.1f} us)")
+            f"sorted state {sorted_state['value']:.3e} (reorder {sorted_state['reorder_us']:.1f} us); "
+            f"host state {host_state}; growing {growing}")
     else:
-        fwd_bwd = batched = sorted_state = None
+        fwd_bwd = batched = sorted_state = host_state = growing = None
 
     cpu = None
     if not args.no_cpu:
@@ -474,6 +577,7 @@ def main():
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
         "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched, "sorted_state": sorted_state,
+        "host_state": host_state, "growing_population": growing,
     }
     print(json.dumps(rec), flush=True)
 

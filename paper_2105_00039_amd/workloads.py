@@ -24,6 +24,12 @@ figure). The recipes below reproduce those shapes synthetically:
                 per-simulation densities and force coefficients.
 * ``targets``   initial positions plus Gaussian noise, used as the regression
                 target of a differentiable rollout.
+* ``grow_and_divide``  a synthetic proliferation rule for variable
+                populations (benchmark A's population grows by cell
+                division; the simulator's own rules are not part of the
+                paper): every diameter grows by a factor, agents above a
+                threshold split into two daughters of half the volume placed
+                symmetrically along a random direction.
 
 Draw order with ``numpy.random.default_rng(seed)`` (PCG64): positions, then
 diameters, then per-simulation parameters, then targets. FP32 inputs are the
@@ -163,6 +169,28 @@ def targets(pop: Population, sigma: float = 1.0, seed: int = 0):
     rng = np.random.default_rng(seed + 1000003)
     noise = rng.normal(0.0, sigma, size=(pop.n, 3))
     return pop.x + noise[:, 0], pop.y + noise[:, 1], pop.z + noise[:, 2]
+
+
+def grow_and_divide(x, y, z, d, rng, growth: float = 1.02, d_max: float = 12.0):
+    """One step of the synthetic proliferation rule on FP64 arrays: d *= growth;
+    every agent with d > d_max divides.  The mother keeps its index and becomes
+    daughter 1 at p + (d/4)u, daughter 2 is appended (in order of the mothers'
+    indices) at p - (d/4)u, both with diameter d / 2^(1/3) (half the volume).
+    u is a unit vector drawn from ``rng`` per dividing agent (normalised
+    Gaussian triple)."""
+    d = d * growth
+    div = np.nonzero(d > d_max)[0]
+    if div.size == 0:
+        return x.copy(), y.copy(), z.copy(), d
+    u = rng.normal(size=(div.size, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    off = (d[div] / 4.0)[:, None] * u
+    dd = d[div] / 2.0 ** (1.0 / 3.0)
+    x, y, z, d = x.copy(), y.copy(), z.copy(), d.copy()
+    px, py, pz = x[div].copy(), y[div].copy(), z[div].copy()
+    x[div], y[div], z[div], d[div] = px + off[:, 0], py + off[:, 1], pz + off[:, 2], dd
+    return (np.concatenate([x, px - off[:, 0]]), np.concatenate([y, py - off[:, 1]]),
+            np.concatenate([z, pz - off[:, 2]]), np.concatenate([d, dd]))
 
 
 # Named workloads.  Sizes follow the paper's benchmarks scaled to this build's

@@ -1,0 +1,62 @@
+"""Variable populations (the shape of the paper's proliferation benchmark):
+a population that grows by a synthetic division rule is stepped on one
+workspace whose agent count changes every build, and on a larger workspace
+once the capacity is exceeded.  Every step is checked against the oracle on
+that step's inputs: grid bit-exact, displacements within the parity bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2105_00039_amd as ms
+from paper_2105_00039_amd import workloads
+from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+
+pytestmark = pytest.mark.gpu
+
+P = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ms._lib.load()
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_growing_population(mode):
+    pop = workloads.uniform(3000, mean_neighbors=12.0, seed=31)
+    x, y, z, d = pop.arrays()
+    rng = np.random.default_rng(32)
+    cap = 4000
+    ws = ms.Workspace(cap, dtype=mode)
+    sizes, rebuilt = [], 0
+    for step in range(10):
+        x, y, z, d = workloads.grow_and_divide(x, y, z, d, rng, growth=1.03)
+        n = len(x)
+        sizes.append(n)
+        arrs = [np.asarray(a).astype(NP_IN[mode]) for a in (x, y, z, d)]
+        if n > cap:
+            with pytest.raises(ms.MechStepError):
+                ms.grid_build(ws, *[torch.from_numpy(a).cuda() for a in arrs])
+            cap = 2 * n
+            ws = ms.Workspace(cap, dtype=mode)
+            rebuilt += 1
+        t = [torch.from_numpy(a).cuda() for a in arrs]
+        ms.grid_build(ws, *t)
+        D = ms.mech_step(ws, P)
+        ms.device_status(ws)
+        o = oracle_inputs(arrs, mode)
+        g = ms.grid_get(ws)
+        box, start, perm = oracle.grid(*o)
+        assert np.array_equal(g["box_id"].cpu().numpy(), box)
+        assert np.array_equal(g["start"].cpu().numpy(), start)
+        assert np.array_equal(g["perm"].cpu().numpy(), perm)
+        _, Do = oracle.step(*o, P)
+        S, A, _ = oracle.tolerance_scales(*o, P["kappa"], P["gamma"], UNIT[mode])
+        Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
+        bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+        check_vectors(Dg, Do, bound, f"growing population step {step} n={n}")
+        x, y, z = (np.asarray(a, np.float64) + Dg[:, k] for k, a in enumerate((x, y, z)))
+    assert sizes[-1] > 2 * 3000 and rebuilt >= 1
