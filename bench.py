@@ -102,6 +102,10 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     gout = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(4))
     gkg = torch.empty(2, dtype=torch.float64, device="cuda")
     gin = tuple(torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+    # contact-list length of the gather picked on this workload, outside the timed region
+    from paper_2105_00039_amd import autotune
+    ms.grid_build(ws, *t)
+    ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
 
     def one(ev=None):
         ms.grid_build(ws, *t)
@@ -331,6 +335,9 @@ def time_batched(ms, torch, steps, warmup, seed=0):
     P = ms.params_tensor([dict(PARAMS, kappa=float(k), gamma=float(g)) for k, g in zip(b.kappa, b.gamma)],
                          "cuda")
     out = tuple(torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+    from paper_2105_00039_amd import autotune
+    ms.grid_build_batched(ws, *t, spec)
+    tuning = autotune.tune(ws, lambda: ms.mech_step_batched(ws, P, out=out))
 
     def one():
         ms.grid_build_batched(ws, *t, spec)
@@ -362,6 +369,7 @@ def time_batched(ms, torch, steps, warmup, seed=0):
     sec = a.elapsed_time(e) / 1e3
     return dict(value=n * steps / sec, unit="agent-steps/s", n_sims=b.n_sims, n_agents=n, steps=steps,
                 ms_per_step=sec / steps * 1e3, dtype="f32 force, f64 positions",
+                gather_list=tuning["choice"],
                 workload="batched256: sizes 10^U(3,5), 4-30 neighbours, kappa U[1,4], gamma U[0.5,2]")
 
 
@@ -499,6 +507,7 @@ def main():
 
     # headline: graph-replayed steps
     sec, _, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True)
+    head_tuning = ws.tuning
     value = N * args.steps / sec
     log(f"graph {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, {value:.3e} agent-steps/s")
     # roofline of the force kernel: eager pass with events around each launch
@@ -530,19 +539,23 @@ def main():
     if not args.no_extras:
         other = "f64" if args.dtype == "f32" else "f32"
         oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
-        s2, _, _, _ = time_plain(ms, torch, oarrs, other, args.steps, args.warmup, graph=True)
+        s2, _, w2, _ = time_plain(ms, torch, oarrs, other, args.steps, args.warmup, graph=True)
         extras[f"plain_{other}_n{args.neighbors:g}"] = N * args.steps / s2
+        extras[f"plain_{other}_n{args.neighbors:g}_gather_list"] = w2.tuning["choice"]
         for nb in (4.0, 30.0):
             p2 = workloads.uniform(N, mean_neighbors=nb, seed=args.seed)
             a2 = [a.astype(np_in) for a in p2.arrays()]
-            s3, _, _, _ = time_plain(ms, torch, a2, args.dtype, args.steps, args.warmup, graph=True)
+            s3, _, w3, _ = time_plain(ms, torch, a2, args.dtype, args.steps, args.warmup, graph=True)
             extras[f"plain_{args.dtype}_n{nb:g}"] = N * args.steps / s3
+            extras[f"plain_{args.dtype}_n{nb:g}_gather_list"] = w3.tuning["choice"]
         # clustered workload: 16,777,216 agents in 64 Gaussian clusters, FP32
         cl = workloads.workload("clusters16M", seed=args.seed)
         carrs = [a.astype(np.float32) for a in cl.arrays()]
         del cl
-        s5, _, _, _ = time_plain(ms, torch, carrs, "f32", args.steps, args.warmup, graph=True)
+        s5, _, w5, _ = time_plain(ms, torch, carrs, "f32", args.steps, args.warmup, graph=True)
         extras["clusters16M_f32"] = carrs[0].size * args.steps / s5
+        extras["clusters16M_f32_gather_list"] = w5.tuning["choice"]
+        del w5
         extras["clusters16M_f32_ms_per_step"] = s5 / args.steps * 1e3
         del carrs
         torch.cuda.empty_cache()
@@ -574,7 +587,8 @@ def main():
         "config": {"workload": name, "n_agents": N, "mean_neighbors_target": args.neighbors,
                    "measured_neighbors": st["neighbors"], "contacts_per_agent": K,
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
-                   "diameters": "U[8,12]", "params": PARAMS, "graph": True},
+                   "diameters": "U[8,12]", "params": PARAMS, "graph": True,
+                   "gather_list": head_tuning["choice"], "gather_list_ms": head_tuning["ms"]},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
         "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched, "sorted_state": sorted_state,
         "host_state": host_state, "growing_population": growing,

@@ -99,7 +99,7 @@ typedef struct {
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
  * fields from n_agents to built are updated by the grid builds.  Treat them as
- * read-only; keep_forces is the caller's to set. */
+ * read-only; keep_forces and gather_list are the caller's to set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -116,7 +116,13 @@ typedef struct {
                             instead of recomputing when the device records that
                             they belong to the current build and the same
                             parameters.  Results are identical either way. */
-    int32_t reserved;
+    int32_t gather_list; /* contact-list length of the forward gather: 0 (set by
+                            ms_workspace_init; means 32), 32 or 40 entries per
+                            lane (anything else: MS_EINVAL from the step calls).
+                            Longer lists drain less often, which pays on dense
+                            populations; shorter ones leave LDS for more blocks
+                            per CU.  Results are identical bit for bit; the
+                            package's autotuner picks the faster one. */
 } ms_workspace;
 
 /* Bytes of device memory a workspace with these capacities needs. */

@@ -25,7 +25,7 @@ __all__ = [
     "Workspace", "BatchSpec", "grid_build", "mech_step", "mech_step_backward",
     "grid_build_batched", "mech_step_batched", "mech_step_backward_batched", "integrate",
     "mech_step_integrate", "mech_step_batched_integrate",
-    "reorder", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
+    "reorder", "grid_info", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
     "params_tensor",
 ]
 
@@ -66,7 +66,8 @@ class Workspace:
     """
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
-                 dtype: str = "f32", device=None, keep_forces: bool = False):
+                 dtype: str = "f32", device=None, keep_forces: bool = False,
+                 gather_list: int = 0):
         self.lib = _lib.load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -84,7 +85,18 @@ class Workspace:
                                               int(max_agents), int(max_boxes), int(max_sims),
                                               self.code, _stream(self.device)))
         self.keep_forces = keep_forces
+        self.gather_list = gather_list
         self.builds = 0   # grid builds issued on this workspace (the autograd layer checks it)
+
+    @property
+    def gather_list(self) -> int:
+        """Contact-list length of the forward gather (0 = default 32, or 32 or
+        40); results do not depend on it, speed does (see autotune)."""
+        return int(self.c.gather_list)
+
+    @gather_list.setter
+    def gather_list(self, v: int):
+        self.c.gather_list = int(v)
 
     @property
     def keep_forces(self) -> bool:
@@ -277,15 +289,22 @@ def reorder(ws: Workspace, src, out=None):
     return out
 
 
-def grid_get(ws: Workspace):
-    """Synchronising export of the last build: per-simulation geometry and the
-    box index, box start and box-sorted order arrays (device int32 tensors)."""
+def grid_info(ws: Workspace):
+    """Synchronising per-simulation geometry of the last build (origin, edge,
+    dims, box count, box base, agent count), without copying any array."""
     B = max(ws.n_sims, 1)
     info = (_lib.ms_grid_info * B)()
     st = ws.lib.ms_grid_get(ctypes.byref(ws.c), info, None, None, None, _stream(ws.device))
     geo = [dict(origin=tuple(i.origin), edge=i.edge, dims=tuple(i.dims), error=i.error,
                 n_boxes=i.n_boxes, box_base=i.box_base, n_agents=i.n_agents) for i in info]
     _lib.check(st)
+    return geo
+
+
+def grid_get(ws: Workspace):
+    """Synchronising export of the last build: per-simulation geometry and the
+    box index, box start and box-sorted order arrays (device int32 tensors)."""
+    geo = grid_info(ws)
     n = ws.n_agents
     total = sum(g["n_boxes"] for g in geo)
     box = torch.empty(n, dtype=torch.int32, device=ws.device)

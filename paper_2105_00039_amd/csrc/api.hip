@@ -114,7 +114,7 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->n_sims = 0;
     ws->built = 0;
     ws->keep_forces = 0;
-    ws->reserved = 0;
+    ws->gather_list = 0;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -162,10 +162,20 @@ ms_status ms_grid_build_batched(ms_workspace* ws, const void* x, const void* y, 
                         "ms_grid_build_batched");
 }
 
+// Contact-list length of the forward gather chosen by the workspace.
+static int gather_list(const ms_workspace* ws)
+{
+    return ws->gather_list == ms::kLongList ? ms::kLongList : ms::kMaxContacts;
+}
+
 static ms_status step_common(const ms_workspace* ws, int want_built, const char* who)
 {
     ms_status st = check_ws(ws, who);
     if (st) return st;
+    if (ws->gather_list != 0 && ws->gather_list != ms::kMaxContacts &&
+        ws->gather_list != ms::kLongList)
+        return fail(MS_EINVAL, "%s: gather_list must be 0, %d or %d", who, ms::kMaxContacts,
+                    ms::kLongList);
     if (ws->built != want_built)
         return fail(MS_EINVAL, "%s: workspace holds no %s grid build", who,
                     want_built == 1 ? "plain" : "batched");
@@ -185,7 +195,7 @@ ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, voi
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
                                       dz, nullptr, nullptr, nullptr, ws->keep_forces != 0,
-                                      as_stream(stream)),
+                                      gather_list(ws), as_stream(stream)),
                      who);
 }
 
@@ -214,7 +224,8 @@ ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, voi
     if ((st = check_step_integrate(ws, x, y, z, dx, dy, dz, who))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
-                                      dz, x, y, z, ws->keep_forces != 0, as_stream(stream)),
+                                      dz, x, y, z, ws->keep_forces != 0, gather_list(ws),
+                                      as_stream(stream)),
                      who);
 }
 
@@ -231,7 +242,7 @@ ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, 
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
                                       params, dx, dy, dz, nullptr, nullptr, nullptr, false,
-                                      as_stream(stream)),
+                                      gather_list(ws), as_stream(stream)),
                      who);
 }
 
@@ -248,7 +259,8 @@ ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params
     if ((st = check_step_integrate(ws, x, y, z, dx, dy, dz, who))) return st;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
-                                      params, dx, dy, dz, x, y, z, false, as_stream(stream)),
+                                      params, dx, dy, dz, x, y, z, false, gather_list(ws),
+                                      as_stream(stream)),
                      who);
 }
 

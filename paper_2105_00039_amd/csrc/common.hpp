@@ -21,6 +21,8 @@ constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in 
 constexpr int kSBMax = 12;
 constexpr int kBucketAgents = 2048;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
+constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
+constexpr int kLongList = 40;         // the longer list the forward gather may use
 
 // Device error bits (ms_grid_info.error and the workspace error word).
 enum : uint32_t {

@@ -13,7 +13,7 @@
 namespace ms {
 namespace {
 
-template <int M, bool BATCHED>
+template <int M, bool BATCHED, int LIST>
 __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
                                                   const int32_t* __restrict__ start,
                                                   const uint32_t* __restrict__ split,
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    __shared__ uint32_t lst[kMaxContacts * kBlock];
+    __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     // forces kept for the backward step: record which build and parameters
     // they belong to (the backward uses them only on a match)
@@ -46,9 +46,8 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
-                         (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                         fx, fy, fz);
+    force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
+                               (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x, fx, fy, fz);
     if (fsave) {
         Pay f;
         f.x = fx; f.y = fy; f.z = fz; f.w = (Real)0;
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                      void* dz, void* px, void* py, void* pz, bool keep, hipStream_t s)
+                      void* dz, void* px, void* py, void* pz, bool keep, int list, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -268,15 +267,23 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
     Real* Y = static_cast<Real*>(dy);
     Real* Z = static_cast<Real*>(dz);
     Pay* A = static_cast<Pay*>(D.pay2);
-    if (batched) {
-        ms_params dummy{};
-        k_force<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n, dummy,
-                                                p_dev, D.hdr, A, nullptr);
-    } else {
-        k_force<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1, n,
-                                                 *p_host, nullptr, D.hdr, A,
-                                                 keep ? static_cast<Pay*>(D.fsave) : nullptr);
-    }
+    Pay* fs = keep ? static_cast<Pay*>(D.fsave) : nullptr;
+    ms_params dummy{};
+    if (batched && list == kLongList)
+        k_force<M, true, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off,
+                                                           B, n, dummy, p_dev, D.hdr, A, nullptr);
+    else if (batched)
+        k_force<M, true, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
+                                                              D.off, B, n, dummy, p_dev, D.hdr, A,
+                                                              nullptr);
+    else if (list == kLongList)
+        k_force<M, false, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
+                                                            nullptr, 1, n, *p_host, nullptr, D.hdr,
+                                                            A, fs);
+    else
+        k_force<M, false, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
+                                                               nullptr, 1, n, *p_host, nullptr,
+                                                               D.hdr, A, fs);
     if (px) {
         using In = typename Mode<M>::In;
         k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),
@@ -326,16 +333,19 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, void* px, void* py, void* pz, bool keep, hipStream_t s)
+                        void* dz, void* px, void* py, void* pz, bool keep, int list,
+                        hipStream_t s)
 {
     switch (L.dtype) {
     case MS_F32:
-        return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep, s);
+        return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
+                                  list, s);
     case MS_F64:
-        return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep, s);
+        return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
+                                  list, s);
     case MS_F32_POS64:
         return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz,
-                                        keep, s);
+                                        keep, list, s);
     default: return hipErrorInvalidValue;
     }
 }

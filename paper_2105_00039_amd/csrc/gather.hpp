@@ -87,7 +87,6 @@ __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int
     }
 }
 
-constexpr int kMaxContacts = 32;   // per-lane contact list length in LDS
 
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
@@ -227,7 +226,7 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
 // drained (by the whole wavefront at once) before a group of four could
 // overflow any lane's list, so pairs are handed over in candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
 // payload bytes.
-template <typename Real, typename Pay, typename OnPair>
+template <typename Real, typename Pay, int LIST = kMaxContacts, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
@@ -236,7 +235,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
                                               OnPair&& on_pair)
 {
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
-    static_assert(kMaxContacts % 4 == 0, "the list drains in groups of four");
+    static_assert(LIST % 4 == 0, "the list drains in groups of four");
     const char* base = reinterpret_cast<const char*>(pay);
     int cnt = 0;
     auto drain = [&]() {
@@ -271,7 +270,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
         for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
             // the whole wave drains when any lane's list is nearly full: the
             // lanes' drains run side by side instead of one after another
-            if (__any(cnt > kMaxContacts - 4)) drain();
+            if (__any(cnt > LIST - 4)) drain();
             // The payload region has three spare entries after the last
             // agent, so the loads past a run's end stay inside it; those
             // slots are masked out of the test.
@@ -290,7 +289,8 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
 // order (contact_force drops non-overlapping pairs and the agent itself).
-template <typename Real, typename Pay>
+// LIST: length of the per-lane contact list `lst` (stride kBlock).
+template <typename Real, typename Pay, int LIST = kMaxContacts>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
@@ -298,7 +298,8 @@ __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& p
                                           uint32_t* lst, Real& fx, Real& fy, Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay>(g, c, pi, self_off, start, split, pay, lst, [&](uint32_t, const Pay& q) {
+    scan_contacts<Real, Pay, LIST>(g, c, pi, self_off, start, split, pay, lst,
+                                   [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });
     fx = ax; fy = ay; fz = az;

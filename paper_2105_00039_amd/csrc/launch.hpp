@@ -21,10 +21,11 @@ hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s)
 // Forward step.  Single: p_host valid, off == nullptr.  Batched: p_dev valid.
 // px/py/pz non-null: positions updated in place (p += Delta); dx/dy/dz may
 // then be null.  keep (single only): also store the forces for the backward
-// step.
+// step.  list: contact-list length of the gather (kMaxContacts or kLongList).
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, void* px, void* py, void* pz, bool keep, hipStream_t s);
+                        void* dz, void* px, void* py, void* pz, bool keep, int list,
+                        hipStream_t s);
 
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,

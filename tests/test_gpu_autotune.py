@@ -1,0 +1,104 @@
+"""The contact-list length of the forward gather (the autotuner's knob) does
+not change any result: plain, fused and batched steps and the backward are
+bitwise identical for every allowed length; the tuner picks an allowed
+length, caches it under its key (dict or JSON file) and reuses it; other
+lengths are rejected through the C ABI."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2105_00039_amd as ms
+from paper_2105_00039_amd import autotune, workloads
+from helpers import NP_IN
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["f64", "f32", "f32_pos64"]
+P = dict(kappa=2.0, gamma=1.0, dt=0.01, max_disp=3.0, adherence=0.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ms._lib.load()
+
+
+def dev(arrs, mode):
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(NP_IN[mode]))).cuda() for a in arrs]
+
+
+def population(name):
+    if name == "uniform20000_n30":
+        return workloads.uniform(20000, mean_neighbors=30.0, seed=41).arrays()
+    return workloads.clusters(20000, n_clusters=3, side=250.0, seed=42).arrays()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("case", ["uniform20000_n30", "clusters20000_dense"])
+def test_list_length_does_not_change_results(case, mode):
+    arrs = population(case)
+    n = len(arrs[0])
+    ws = ms.Workspace(n, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t)
+    g = [torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3)]
+    res = {}
+    for L in (32, 40):
+        ws.gather_list = L
+        D = [a.clone() for a in ms.mech_step(ws, P)]
+        G = [a.clone() for a in ms.mech_step_backward(ws, P, *g)[:4]]
+        pos = [a.clone() for a in t[:3]]
+        ms.mech_step_integrate(ws, P, *pos)
+        res[L] = D + G + pos
+    ms.device_status(ws)
+    for a, b in zip(res[32], res[40]):
+        assert torch.equal(a, b)
+
+
+def test_list_length_batched():
+    b = workloads.batched(n_sims=10, log10_min=2.0, log10_max=3.7, seed=43)
+    prms = [dict(P, kappa=float(k), gamma=float(gm)) for k, gm in zip(b.kappa, b.gamma)]
+    Pd = ms.params_tensor(prms, "cuda")
+    ws = ms.Workspace(b.n, max_sims=b.n_sims, dtype="f32_pos64")
+    ms.grid_build_batched(ws, *dev(b.arrays(), "f32_pos64"), ms.BatchSpec(b.offsets))
+    out = {}
+    for L in (32, 40):
+        ws.gather_list = L
+        out[L] = [a.clone() for a in ms.mech_step_batched(ws, Pd)]
+    ms.device_status(ws)
+    for a, c in zip(out[32], out[40]):
+        assert torch.equal(a, c)
+
+
+def test_tuner_picks_caches_and_rejects(tmp_path):
+    arrs = population("uniform20000_n30")
+    n = len(arrs[0])
+    ws = ms.Workspace(n, dtype="f32")
+    ms.grid_build(ws, *dev(arrs, "f32"))
+    out = tuple(torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+
+    def step():
+        ms.mech_step(ws, P, out=out)
+
+    table = {}
+    r = autotune.tune(ws, step, cache=table)
+    assert r["source"] == "timed" and r["choice"] in autotune.CHOICES
+    assert ws.gather_list == r["choice"] and table[r["key"]] == r["choice"]
+    ws.gather_list = 0
+    r2 = autotune.tune(ws, step, cache=table)
+    assert r2["source"] == "cache" and ws.gather_list == r["choice"]
+    path = tmp_path / "tune.json"
+    r3 = autotune.tune(ws, step, key="custom", cache=path)
+    assert r3["source"] == "timed" and json.loads(path.read_text())["custom"] == r3["choice"]
+    r4 = autotune.tune(ws, step, key="custom", cache=path)
+    assert r4["source"] == "cache" and r4["choice"] == r3["choice"]
+    ws.gather_list = 33
+    with pytest.raises(ms.MechStepError) as ei:
+        ms.mech_step(ws, P)
+    assert ei.value.status == ms._lib.MS_EINVAL
+    ws.gather_list = 0
+    ms.mech_step(ws, P)
+    ms.device_status(ws)
