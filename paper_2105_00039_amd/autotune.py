@@ -46,10 +46,13 @@ def _load(cache):
     return {}, path
 
 
-def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache=None) -> dict:
+def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache=None,
+         margin: float = 0.02) -> dict:
     """Pick the fastest contact-list length for ``step`` (a callable running one
     force step on the workspace's current build, e.g. ``lambda: mech_step(ws,
-    params, out=out)``) and set it on ``ws``.
+    params, out=out)``) and set it on ``ws``.  The first of ``choices`` (the
+    library default) is kept unless another is faster by more than ``margin``,
+    so a tie does not flip the choice from run to run.
 
     cache: None, a dict, or the path of a JSON file (read if present, written
     after a timed choice).  Returns {"key", "choice", "source": "cache" |
@@ -72,6 +75,8 @@ def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache
         torch.cuda.synchronize()
         times[c] = a.elapsed_time(b) / reps
     best = min(times, key=times.get)
+    if times[choices[0]] <= times[best] * (1.0 + margin):
+        best = choices[0]
     ws.gather_list = best
     table[key] = best
     if path is not None:

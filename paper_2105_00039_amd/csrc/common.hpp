@@ -19,7 +19,7 @@ constexpr int kTileA = 4096;          // agents per block in the bucket histogra
 constexpr int kBucketsMax = 4096;     // bucket count limit of the two-level sort
 constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in [6, 12]
 constexpr int kSBMax = 12;
-constexpr int kBucketAgents = 2048;   // target mean agents per bucket
+constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
