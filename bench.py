@@ -462,6 +462,8 @@ def main():
     ap.add_argument("--workload", default="uniform2M", choices=["uniform2M", "clusters16M"],
                     help="with --profile-only: the population of the eager pass (clusters16M: "
                          "16,777,216 agents in 64 Gaussian clusters, FP32)")
+    ap.add_argument("--backward", action="store_true",
+                    help="with --profile-only: eager steps with the backward step as well")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="with --profile-only: also run the copy probe once on MIB MiB "
                          "(the known-size kernel that scales rocprofv3 byte counters)")
@@ -493,7 +495,8 @@ def main():
             arrs = [a.astype(np.float32) for a in cl.arrays()]
             args.dtype = "f32"
             log(f"workload clusters16M f32: {arrs[0].size} agents")
-        sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
+        sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True,
+                                     backward=args.backward)
         log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
         if args.probe_copy:
             nbytes = args.probe_copy << 20
