@@ -16,7 +16,7 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBoundsChunk = kBlock * 16;   // agents per block in the bounds pass
 constexpr int kTileThreads = 1024;    // threads per block of the bucket histogram/partition
 constexpr int kTileA = 4096;          // agents per block in the bucket histogram/partition
-constexpr int kBucketsMax = 4096;     // bucket count limit of the two-level sort
+constexpr int kBucketsMax = 8192;     // bucket count limit of the two-level sort
 constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in [6, 12]
 constexpr int kSBMax = 12;
 constexpr int kBucketAgents = 3072;   // target mean agents per bucket
