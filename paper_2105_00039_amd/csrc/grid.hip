@@ -831,11 +831,22 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     // 3. agents into their box range (arrival order)
     if (staged) {
-        for (int e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-            const int kq = key2[e];
-            const int slot = atomicAdd(&c[kq >> 2], 1);
-            mem[slot] = idx2[e];
-            memq[slot] = (uint8_t)(kq & 3);
+        // at most U agents per thread: every load issued before the LDS work
+        constexpr int U = kSortStage / kSortThreads;
+        int kq[U], id[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = s0 + threadIdx.x + u * kSortThreads;
+            kq[u] = e < s1 ? key2[e] : -1;
+            id[u] = e < s1 ? idx2[e] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (kq[u] >= 0) {
+                const int slot = atomicAdd(&c[kq[u] >> 2], 1);
+                mem[slot] = id[u];
+                memq[slot] = (uint8_t)(kq[u] & 3);
+            }
         }
     } else {
         for (int e0 = s0 + threadIdx.x; e0 < s1; e0 += 4 * kSortThreads) {
@@ -875,11 +886,31 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         inv[bs + r] = e - s0;
     }
     __syncthreads();
-    // 5. write the sorted bucket in slot order
-    for (int p = threadIdx.x; p < s1 - s0; p += kSortThreads) {
-        const int e = s0 + inv[p];
-        perm[s0 + p] = idx2[e];
-        pay[s0 + p] = pay2[e];
+    // 5. write the sorted bucket in slot order (loads issued before the stores)
+    if (s1 > s0) {   // block-uniform; padding lanes read slot s0
+        constexpr int U = kSortStage / kSortThreads;
+        const int cnt = s1 - s0;
+        int e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = threadIdx.x + u * kSortThreads;
+            e[u] = s0 + (p < cnt ? inv[p] : 0);
+        }
+        int32_t id[U];
+        typename Mode<M>::Pay q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            id[u] = idx2[e[u]];
+            q[u] = pay2[e[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = threadIdx.x + u * kSortThreads;
+            if (p < cnt) {
+                perm[s0 + p] = id[u];
+                pay[s0 + p] = q[u];
+            }
+        }
     }
 }
 
