@@ -212,3 +212,48 @@ def test_plain_graph_replay_matches_eager():
         torch.cuda.synchronize()
         for k in range(3):
             assert torch.equal(t[k], ref[s][k]), (s, k)
+
+
+@pytest.mark.parametrize("mode", ["f32_pos64", "f64"])
+def test_batched_dense_cluster_buckets(mode):
+    """A batch whose middle simulation is one tight cluster in a box-rich
+    domain: buckets of the shared sort above the 4096-agent LDS stage and
+    boxes above 255 agents, next to ordinary uniform simulations.  Grid of
+    every simulation bit-exact; displacements of the dense simulation and of
+    sampled agents of the others within the parity bound."""
+    r = np.random.default_rng(91)
+    c = r.normal(0.0, 22.0, size=(19992, 3))
+    corners = np.array([[sx, sy, sz] for sx in (-400.0, 400.0) for sy in (-400.0, 400.0)
+                        for sz in (-400.0, 400.0)])
+    dense = np.concatenate([c, corners])
+    sims = [workloads.uniform(3000, mean_neighbors=12.0, seed=92).arrays(),
+            (dense[:, 0], dense[:, 1], dense[:, 2], r.uniform(8, 12, 20000)),
+            workloads.uniform(5000, mean_neighbors=30.0, seed=93).arrays()]
+    sizes = [len(s[0]) for s in sims]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    arrs = [np.concatenate([s[k] for s in sims]) for k in range(4)]
+    n = int(offsets[-1])
+    ws = ms.Workspace(n, max_boxes=600_000, max_sims=3, dtype=mode)
+    ms.grid_build_batched(ws, *dev(arrs, mode), ms.BatchSpec(offsets))
+    prms = [dict(BASE, kappa=2.0, gamma=1.0)] * 3
+    D = ms.mech_step_batched(ws, ms.params_tensor(prms, "cuda"))
+    ms.device_status(ws)
+    g = ms.grid_get(ws)
+    box = g["box_id"].cpu().numpy()
+    start = g["start"].cpu().numpy()
+    perm = g["perm"].cpu().numpy()
+    Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
+    base = 0
+    for s in range(3):
+        a0, a1 = int(offsets[s]), int(offsets[s + 1])
+        o = oracle_inputs([a[a0:a1] for a in arrs], mode)
+        obox, ostart, operm = oracle.grid(*o)
+        nb = len(ostart) - 1
+        assert np.array_equal(box[a0:a1], obox + base), s
+        assert np.array_equal(start[base:base + nb + 1], ostart + a0), s
+        assert np.array_equal(perm[a0:a1], operm + a0), s
+        idx = np.arange(a1 - a0) if s == 1 else r.choice(a1 - a0, 200, replace=False)
+        _, Do, S, A, _ = oracle.sample(*o, prms[s], idx, UNIT[mode])
+        bound = BASE["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
+        check_vectors(Dg[a0 + idx], Do, bound, f"dense batch sim {s}")
+        base += nb
