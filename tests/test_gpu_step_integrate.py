@@ -102,3 +102,43 @@ def test_fused_step_errors_and_failed_build():
         ms.device_status(ws)
     for u, v in zip(before, tb):
         assert torch.equal(torch.nan_to_num(u, nan=-1.0), torch.nan_to_num(v, nan=-1.0))
+
+
+@pytest.mark.parametrize("mode", ["f32", "f32_pos64"])
+def test_fused_step_graph_replay_matches_eager(mode):
+    """Build + fused step captured in a HIP graph (as the benchmark times it):
+    every replay equals the eager trajectory bit for bit, with eager work and
+    synchronisations between the replays."""
+    arrs = workloads.uniform(40009, mean_neighbors=12.0, seed=23).arrays()
+    n = len(arrs[0])
+    ws = ms.Workspace(n, dtype=mode)
+    out = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+
+    def one(ts):
+        ms.grid_build(ws, *ts)
+        ms.mech_step_integrate(ws, P, *ts[:3], out=out)
+
+    te = dev(arrs, mode)
+    ref = []
+    for _ in range(3):
+        one(te)
+        ref.append([a.clone() for a in te[:3]] + [d.clone() for d in out])
+    t = dev(arrs, mode)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        one(dev(arrs, mode))
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        one(t)
+    for a, v in zip(t, dev(arrs, mode)):
+        a.copy_(v)
+    for s in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        ms.device_status(ws)                     # eager work between replays
+        got = [a for a in t[:3]] + list(out)
+        for k in range(6):
+            assert torch.equal(got[k], ref[s][k]), (s, k)
