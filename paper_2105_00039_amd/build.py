@@ -26,6 +26,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add fusion: results must not depend on how a
+    # function was inlined into a kernel; the kernels write the fused
+    # multiply-adds they want explicitly (fmad in gather.hpp)
+    "-ffp-contract=off",
     "-I", INC, "-I", SRC,
 ]
 

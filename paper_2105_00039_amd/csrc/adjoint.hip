@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
             pin(fj);
             const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-            const Real l2 = ux * ux + uy * uy + uz * uz;
+            const Real l2 = len2(ux, uy, uz);
             const Real rs = pi.w + q.w;
             const Real l = fsqrt(l2);
             const Real delta = rs - l;

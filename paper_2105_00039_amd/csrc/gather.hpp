@@ -88,6 +88,20 @@ __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int
 }
 
 
+// Explicit fused multiply-add (a*b + c, one rounding).  The library is built
+// without implicit contraction, so every fusion in the force arithmetic is
+// written here and the same expression rounds the same way in every kernel
+// that inlines it.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Squared length of (ux, uy, uz).
+template <typename Real>
+__device__ __forceinline__ Real len2(Real ux, Real uy, Real uz)
+{
+    return fmad(uz, uz, fmad(ux, ux, uy * uy));
+}
+
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
 // a reciprocal.
@@ -95,17 +109,17 @@ __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float k
                                               float& ax, float& ay, float& az)
 {
     const float ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-    const float l2 = ux * ux + uy * uy + uz * uz;
+    const float l2 = len2(ux, uy, uz);
     const float rs = pi.w + q.w;
     const float il = __builtin_amdgcn_rsqf(l2);
-    const float delta = rs - l2 * il;
+    const float delta = fmad(-l2, il, rs);
     if (delta > 0.0f && l2 > 0.0f) {
         const float rho = pi.w * q.w * __builtin_amdgcn_rcpf(rs);
-        const float sv = kap * delta - gam * __builtin_amdgcn_sqrtf(rho * delta);
+        const float sv = fmad(kap, delta, -gam * __builtin_amdgcn_sqrtf(rho * delta));
         const float sl = sv * il;
-        ax += sl * ux;
-        ay += sl * uy;
-        az += sl * uz;
+        ax = fmad(sl, ux, ax);
+        ay = fmad(sl, uy, ay);
+        az = fmad(sl, uz, az);
     }
 }
 
@@ -113,17 +127,17 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
                                               double& ax, double& ay, double& az)
 {
     const double ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-    const double l2 = ux * ux + uy * uy + uz * uz;
+    const double l2 = len2(ux, uy, uz);
     const double rs = pi.w + q.w;
     const double l = sqrt(l2);
     const double delta = rs - l;
     if (delta > 0.0 && l2 > 0.0) {
         const double rho = pi.w * q.w / rs;
-        const double sv = kap * delta - gam * sqrt(rho * delta);
+        const double sv = fmad(kap, delta, -gam * sqrt(rho * delta));
         const double sl = sv / l;
-        ax += sl * ux;
-        ay += sl * uy;
-        az += sl * uz;
+        ax = fmad(sl, ux, ax);
+        ay = fmad(sl, uy, ay);
+        az = fmad(sl, uz, az);
     }
 }
 
@@ -258,7 +272,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
     auto test = [&](Pay q, uint32_t off, bool live) {
         pin(q);
         const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-        const Real l2 = ux * ux + uy * uy + uz * uz;
+        const Real l2 = len2(ux, uy, uz);
         const Real rs = pi.w + q.w;
         lst[cnt * kBlock] = off;
         cnt += (int)(live & (l2 < rs * rs));

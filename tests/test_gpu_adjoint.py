@@ -194,12 +194,16 @@ def test_rollout_gradient_central_differences_gpu_f64():
 
 
 @pytest.mark.parametrize("mode", ["f64", "f32", "f32_pos64"])
-def test_kept_forces_give_identical_results(mode):
-    """A forward step that keeps its forces lets the backward skip the
-    recompute only for the same build and parameters; results are identical
-    bit for bit to the recomputing path, and a new build or other parameters
-    fall back to the recompute."""
-    pop = workloads.uniform(20000, mean_neighbors=12.0, seed=8)
+@pytest.mark.parametrize("case", ["uniform_n12", "dense_clusters"])
+def test_kept_forces_give_identical_results(mode, case):
+    """A forward step that keeps its forces lets the backward skip the force
+    recompute only for the same build and parameters; forward and backward
+    results are identical bit for bit to the recomputing path, and a new build
+    or other parameters fall back to the recompute.  The dense case has
+    clamped agents, whose displacement arithmetic must round the same way in
+    the keeping and the plain force kernel."""
+    pop = workloads.uniform(20000, mean_neighbors=12.0, seed=8) if case == "uniform_n12" else \
+        workloads.clusters(20000, n_clusters=3, side=250.0, seed=42)
     n = pop.n
     rng = np.random.default_rng(8)
     g = dev(rng.normal(size=(3, n)), "f64" if mode == "f64" else "f32")
