@@ -123,13 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_split4(const Pay* __restrict__ in, i
 }
 
 // Deterministic block sum: butterfly inside each wave, waves in fixed order.
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum_fixed(double v, double* s_w)
 {
     v = wave_sum<double>(v);
     if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = v;
     __syncthreads();
     double t = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+    for (int w = 0; w < NT / kWave; ++w) t += s_w[w];
     __syncthreads();
     return t;
 }
@@ -189,12 +190,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             const Real l = fsqrt(l2);
             const Real delta = rs - l;
             if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
-            const Real il = (Real)1 / l;
+            const Real il = rdiv((Real)1, l);
             const Real ex = ux * il, ey = uy * il, ez = uz * il;
-            const Real rho = pi.w * q.w / rs;
+            const Real rho = rdiv(pi.w * q.w, rs);
             const Real sq = fsqrt(rho * delta);
             const Real sv = kap * delta - gam * sq;
-            const Real h = (Real)0.5 / sq;
+            const Real h = rdiv((Real)0.5, sq);
             const Real s_d = kap - gam * rho * h;
             const Real s_r = -gam * delta * h;
             const Real wx = fi.x - fj.x, wy = fi.y - fj.y, wz = fi.z - fj.z;
@@ -239,12 +240,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
 }
 
 // One block per simulation: sum the partials of the blocks it overlaps.
-__global__ __launch_bounds__(kBlock) void k_reduce_params(const double* __restrict__ partials,
+constexpr int kReduceThreads = 1024;   // threads of the one block per simulation
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_params(const double* __restrict__ partials,
                                                           const int64_t* __restrict__ off,
                                                           int64_t n, const Header* __restrict__ hdr,
                                                           double* __restrict__ out)
 {
-    __shared__ double s_w[kBlock / kWave];
+    __shared__ double s_w[kReduceThreads / kWave];
     if (hdr->error) return;
     const int s = blockIdx.x;
     const int64_t a0 = off ? off[s] : 0;
@@ -253,13 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_params(const double* __restri
     if (a1 > a0) {
         const int64_t c0 = a0 / kBlock, c1 = (a1 - 1) / kBlock;
         const int64_t sh = off ? s : 0;
-        for (int64_t c = c0 + threadIdx.x; c <= c1; c += kBlock) {
+        for (int64_t c = c0 + threadIdx.x; c <= c1; c += kReduceThreads) {
             tk += partials[2 * (c + sh)];
             tg += partials[2 * (c + sh) + 1];
         }
     }
-    tk = block_sum_fixed(tk, s_w);
-    tg = block_sum_fixed(tg, s_w);
+    tk = block_sum_fixed<kReduceThreads>(tk, s_w);
+    tg = block_sum_fixed<kReduceThreads>(tg, s_w);
     if (threadIdx.x == 0) {
         out[2 * s] = tk;
         out[2 * s + 1] = tg;
@@ -289,7 +292,7 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
                                                    dummy, p_dev, D.hdr, rec, fb, nullptr);
         k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
                                                      n, dummy, p_dev, D.hdr, rec, D.partials);
-        k_reduce_params<<<B, kBlock, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
+        k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
         k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
@@ -297,7 +300,7 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
         k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
                                                       D.partials);
-        k_reduce_params<<<1, kBlock, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
+        k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
     }
     k_split4<Pay, Real><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, OX, OY, OZ, OD);
     return hipGetLastError();
