@@ -106,3 +106,20 @@ def test_workspace_struct_mirror_matches_header():
     for (ty, name), (_, cty) in zip(decl, mirror):
         assert ctypes.sizeof(cty) == width[ty], name
     assert ctypes.sizeof(_lib.ms_workspace) == sum(width[t] for t, _ in decl)
+
+
+def test_header_is_plain_c99(tmp_path):
+    """The boundary header compiles as C99 on its own (plain pointers and
+    sizes, no HIP or torch types), so any C caller can use it."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "mechstep.h"\n'
+                   "int main(void) { ms_workspace w; ms_params p; ms_grid_info g;\n"
+                   "  (void)w; (void)p; (void)g; return 0; }\n")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
