@@ -470,7 +470,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the step has no multi-GPU path in this build).", file=sys.stderr)
+              "(the step runs on a single GPU).", file=sys.stderr)
         sys.exit(2)
 
     import torch
