@@ -116,7 +116,7 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     L.box_id = take(4 * (size_t)na);
     L.quarter = take((size_t)na);
     L.start = take(4 * (size_t)(max_boxes + 2));
-    L.split = take(4 * (size_t)(max_boxes + 2));
+    L.split = take(8 * (size_t)(max_boxes + 2));
     L.hist = take(4 * (size_t)(L.nb_cap * L.nblk_a_max));
     L.bstart = take(4 * (size_t)(2 * L.nb_cap + 2));
     L.key2 = take(4 * (size_t)na);
@@ -144,7 +144,7 @@ struct Dev {
     int32_t* box_id;    // box index per agent, caller order
     uint8_t* quarter;   // x-quarter of each agent inside its box, caller order
     int32_t* start;     // box start offsets [total boxes + 1]
-    uint32_t* split;    // per box: quarter split offsets (split_word)
+    uint32_t* split;    // per box b: [2b] = start[b], [2b + 1] = quarter split word
     int32_t* hist;      // [bucket][block-A] histogram, scanned in place along each row
     int32_t* bstart;    // [0, nb]: bucket starts; [nb_cap+1 ...]: bucket totals
     int32_t* key2;      // build: (box in bucket) << 2 | quarter, bucket order

@@ -205,22 +205,24 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
         qa[r] = ta < 0 ? 0 : (ta > 3 ? 3 : ta);
         qb[r] = tb < 0 ? 0 : (tb > 3 ? 3 : tb);
     }
-    int sa[9], sb[9];
-    uint32_t wa[9], wb[9];
-    const char* sbase = reinterpret_cast<const char*>(start);
+    // (start, split word) of the two end boxes: one 8-byte load each.  The
+    // run ends at the end box's start plus its count (byte 3 of its split
+    // word), or at the next box's start when the word holds no count.
+    uint2 pa[9], pb[9];
     const char* wbase = reinterpret_cast<const char*>(split);
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-        sa[r] = *reinterpret_cast<const int32_t*>(sbase + i0[r]);
-        sb[r] = *reinterpret_cast<const int32_t*>(sbase + i1[r] + 4u);
-        wa[r] = *reinterpret_cast<const uint32_t*>(wbase + i0[r]);
-        wb[r] = *reinterpret_cast<const uint32_t*>(wbase + i1[r]);
+        pa[r] = *reinterpret_cast<const uint2*>(wbase + 2u * i0[r]);
+        pb[r] = *reinterpret_cast<const uint2*>(wbase + 2u * i1[r]);
     }
     Runs R;
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-        const int b = sa[r] + split_skip(wa[r], qa[r]);
-        const int en = sb[r] - split_cut(wb[r], qb[r]);
+        const uint32_t wb = pb[r].y;
+        int sb = (int)pb[r].x + (int)(wb >> 24);
+        if (wb == kSplitNone) sb = start[i1[r] / 4u + 1u];
+        const int b = (int)pa[r].x + split_skip(pa[r].y, qa[r]);
+        const int en = sb - split_cut(wb, qb[r]);
         R.b[r] = b;
         R.e[r] = (okr[r] && en > b) ? en : b;
     }

@@ -717,7 +717,9 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                     r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
                     w += split_inc(qm);
                 }
-                if (r == 0) split[b0 + k] = split_word(w, be - bs);
+                if (r == 0)
+                    reinterpret_cast<uint2*>(split)[b0 + k] =
+                        make_uint2((uint32_t)(s0 + cs + bs), split_word(w, be - bs));
                 inv[bs + r] = j;
             }
             __syncthreads();
@@ -753,7 +755,8 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                     const int qm = key2[s0 + pm] & 3;
                     r += (qm < q || (qm == q && idx2[s0 + pm] < orig)) ? 1 : 0;
                 }
-                if (r == 0) split[b0 + k] = kSplitNone;
+                if (r == 0)
+                    reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + cs), kSplitNone);
                 perm[s0 + cs + r] = orig;
                 pay[s0 + cs + r] = pay2[s0 + pe];
             }
@@ -825,7 +828,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         const int32_t v = c[k];
         c[k] = run;
         start[b0 + k] = s0 + run;
-        if (v == 0) split[b0 + k] = 0u;
+        if (v == 0) reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + run), 0u);
         run += v;
     }
     __syncthreads();
@@ -882,7 +885,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
             r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
             w += split_inc(qm);
         }
-        if (r == 0) split[b0 + k] = split_word(w, be - bs);
+        if (r == 0)
+            reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + bs), split_word(w, be - bs));
         inv[bs + r] = e - s0;
     }
     __syncthreads();
