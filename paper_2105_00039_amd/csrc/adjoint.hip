@@ -29,7 +29,7 @@
 namespace ms {
 namespace {
 
-template <int M, bool BATCHED>
+template <int M, bool BATCHED, int LIST>
 __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay* __restrict__ pay,
                                                      const int32_t* __restrict__ start,
                                                      const uint32_t* __restrict__ split,
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    __shared__ uint32_t lst[kMaxContacts * kBlock];
+    __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
         const Pay f = fsave[k];
         fx = f.x; fy = f.y; fz = f.z;
     } else {
-        force_sum<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
+        force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                              (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                              fx, fy, fz);
     }
@@ -135,7 +135,7 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* s_w)
     return t;
 }
 
-template <int M, bool BATCHED>
+template <int M, bool BATCHED, int LIST>
 __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::Pay* __restrict__ pay,
                                                        const typename Mode<M>::Pay* __restrict__ fbar,
                                                        const int32_t* __restrict__ start,
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
     using Pay = typename Mode<M>::Pay;
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
-    __shared__ uint32_t lst[kMaxContacts * kBlock];
+    __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     const unsigned vb = xcd_block();   // partials are indexed by this virtual block
     const int64_t k0 = (int64_t)vb * kBlock;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
         const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        scan_contacts<Real, Pay>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
+        scan_contacts<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
                                  lst + threadIdx.x,
                                  [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
@@ -269,11 +269,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_params(const double* 
     }
 }
 
-template <int M>
-hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
-                         const ms_params* p_host, const ms_params* p_dev, const void* gdx,
-                         const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
-                         double* g_params, hipStream_t s)
+template <int M, int LIST>
+hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                        const ms_params* p_host, const ms_params* p_dev, const void* gdx,
+                        const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
+                        double* g_params, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -288,16 +288,16 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
     Pay* rec = static_cast<Pay*>(D.pay2);
     k_pack3<Pay, Real><<<nb, kBlock, 0, s>>>(GX, GY, GZ, n, D.hdr, rec);
     if (batched) {
-        k_bwd_fbar<M, true><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
+        k_bwd_fbar<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
                                                    dummy, p_dev, D.hdr, rec, fb, nullptr);
-        k_bwd_gather<M, true><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
+        k_bwd_gather<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
                                                      n, dummy, p_dev, D.hdr, rec, D.partials);
         k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
-        k_bwd_fbar<M, false><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
+        k_bwd_fbar<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
                                                     static_cast<const Pay*>(D.fsave));
-        k_bwd_gather<M, false><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
+        k_bwd_gather<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
                                                       D.partials);
         k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
@@ -306,23 +306,38 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
     return hipGetLastError();
 }
 
+// list: contact-list length of the gathers (the workspace's choice for the
+// forward step; results do not depend on it).
+template <int M>
+hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
+                         const ms_params* p_host, const ms_params* p_dev, const void* gdx,
+                         const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
+                         double* g_params, int list, hipStream_t s)
+{
+    if (list == kLongList)
+        return backward_run<M, kLongList>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
+                                          gz, gd, g_params, s);
+    return backward_run<M, kMaxContacts>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
+                                         gz, gd, g_params, s);
+}
+
 }  // namespace
 
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, hipStream_t s)
+                           void* gd, double* g_params, int list, hipStream_t s)
 {
     switch (L.dtype) {
     case MS_F32:
         return backward_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, s);
+                                     gd, g_params, list, s);
     case MS_F64:
         return backward_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, s);
+                                     gd, g_params, list, s);
     case MS_F32_POS64:
         return backward_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx,
-                                           gy, gz, gd, g_params, s);
+                                           gy, gz, gd, g_params, list, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -283,7 +283,8 @@ static ms_status backward_common(const ms_workspace* ws, bool batched, const ms_
     if ((st = check_arrays(who, out_size(ws->dtype), {gdx, gdy, gdz, gx, gy, gz, gd}))) return st;
     return check_hip(ms::launch_backward(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
                                          batched, batched ? nullptr : p, batched ? p : nullptr, gdx,
-                                         gdy, gdz, gx, gy, gz, gd, g_params, as_stream(stream)),
+                                         gdy, gdz, gx, gy, gz, gd, g_params, gather_list(ws),
+                                         as_stream(stream)),
                      who);
 }
 

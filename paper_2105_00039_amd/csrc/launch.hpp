@@ -27,10 +27,11 @@ hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
                         void* dz, void* px, void* py, void* pz, bool keep, int list,
                         hipStream_t s);
 
+// Backward step; list: contact-list length of its gathers (as launch_force).
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, hipStream_t s);
+                           void* gd, double* g_params, int list, hipStream_t s);
 
 hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                             const void* dz, int64_t n, int dtype, hipStream_t s);
