@@ -459,9 +459,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the eager K-step pass (for rocprofv3 runs)")
-    ap.add_argument("--workload", default="uniform2M", choices=["uniform2M", "clusters16M"],
+    ap.add_argument("--workload", default="uniform2M", choices=["uniform2M", "clusters16M", "batched256"],
                     help="with --profile-only: the population of the eager pass (clusters16M: "
-                         "16,777,216 agents in 64 Gaussian clusters, FP32)")
+                         "16,777,216 agents in 64 Gaussian clusters, FP32; batched256: the "
+                         "batched line's 256 simulations, graph-replayed steps)")
     ap.add_argument("--backward", action="store_true",
                     help="with --profile-only: eager steps with the backward step as well")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
@@ -489,6 +490,12 @@ def main():
     log(f"workload {name} {args.dtype}: {N} agents, cube side {pop.meta['side']:.1f}")
 
     if args.profile_only:
+        if args.workload == "batched256":
+            del pop, arrs
+            b = time_batched(ms, torch, args.steps, args.warmup)
+            log(f"batched {b['n_sims']} simulations, {b['n_agents']} agents: {b['ms_per_step']:.3f} ms/step, "
+                f"{b['value']:.3e} agent-steps/s, list {b['gather_list']}")
+            return
         if args.workload == "clusters16M":
             del pop, arrs
             cl = workloads.workload("clusters16M", seed=args.seed)

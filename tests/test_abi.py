@@ -123,3 +123,20 @@ def test_header_is_plain_c99(tmp_path):
                         "-fsyntax-only", "-I", os.path.dirname(HEADER), str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built HIP library the package raises instead of falling
+    back to anything else, and no product module reaches the oracle."""
+    from paper_2105_00039_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libmechstep.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        _lib.load()
+    pkg = os.path.join(ROOT, "paper_2105_00039_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liborc" not in text, f
