@@ -41,10 +41,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
                                                      const Header* __restrict__ hdr,
                                                      const typename Mode<M>::Pay* __restrict__ gin,
                                                      typename Mode<M>::Pay* __restrict__ fbar,
-                                                     const typename Mode<M>::Pay* __restrict__ fsave)
+                                                     const typename Mode<M>::Pay* __restrict__ fsave,
+                                                     const F4* __restrict__ pay32)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
+    constexpr bool PRE = M == MS_F64 && !BATCHED;   // plain FP64 builds scan their FP32 copy
     __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
@@ -61,9 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
         const Pay f = fsave[k];
         fx = f.x; fy = f.y; fz = f.z;
     } else {
-        force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
-                             (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                             fx, fy, fz);
+        force_sum<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
+                                        pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                                        pre32_of<PRE>(pay32, k, g), fx, fy, fz);
     }
     const Pay gr = gin[perm[k]];
     const Real gx = gr.x, gy = gr.y, gz = gr.z;
@@ -147,10 +149,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
                                                        const ms_params* __restrict__ pB,
                                                        const Header* __restrict__ hdr,
                                                        typename Mode<M>::Pay* __restrict__ gout,
-                                                       double* __restrict__ partials)
+                                                       double* __restrict__ partials,
+                                                       const F4* __restrict__ pay32)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
+    constexpr bool PRE = M == MS_F64 && !BATCHED;   // plain FP64 builds scan their FP32 copy
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
     __shared__ uint32_t lst[LIST * kBlock];
@@ -178,9 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
         const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        scan_contacts<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
-                                 lst + threadIdx.x,
-                                 [&](uint32_t off, const Pay& q) {
+        scan_contacts<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start,
+                                            split, pay, lst + threadIdx.x,
+                                            pre32_of<PRE>(pay32, k, g),
+                                            [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
             Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
             pin(fj);
@@ -289,17 +294,17 @@ hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
     k_pack3<Pay, Real><<<nb, kBlock, 0, s>>>(GX, GY, GZ, n, D.hdr, rec);
     if (batched) {
         k_bwd_fbar<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
-                                                   dummy, p_dev, D.hdr, rec, fb, nullptr);
+                                                   dummy, p_dev, D.hdr, rec, fb, nullptr, D.pay32);
         k_bwd_gather<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
-                                                     n, dummy, p_dev, D.hdr, rec, D.partials);
+                                                     n, dummy, p_dev, D.hdr, rec, D.partials, D.pay32);
         k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
     } else {
         k_bwd_fbar<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
-                                                    static_cast<const Pay*>(D.fsave));
+                                                    static_cast<const Pay*>(D.fsave), D.pay32);
         k_bwd_gather<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
-                                                      D.partials);
+                                                      D.partials, D.pay32);
         k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
     }
     k_split4<Pay, Real><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, OX, OY, OZ, OD);

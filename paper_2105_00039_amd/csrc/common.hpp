@@ -84,7 +84,7 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
     size_t hdr, geom, off, bpart, box_id, quarter, start, split, hist, bstart, key2, idx2, pay2,
-        tmp, perm, payload, fbar, fsave, partials, scratch64, total;
+        tmp, perm, payload, pay32, fbar, fsave, partials, scratch64, total;
     int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
@@ -126,6 +126,9 @@ inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sim
     L.perm = take(4 * (size_t)na);
     // three extra entries: the gather reads up to three slots past a run's end
     L.payload = take(pay * (size_t)(na + 3));
+    // FP64 builds of one simulation: a 16-byte FP32 copy of each slot for the
+    // gather's candidate test (same three extra entries)
+    L.pay32 = take(dtype == MS_F64 ? sizeof(F4) * (size_t)(na + 3) : 0);
     L.fbar = take(pay * (size_t)na);
     L.fsave = take(pay * (size_t)na);
     L.partials = take(16 * (size_t)L.n_part);
@@ -158,6 +161,7 @@ struct Dev {
     int32_t* canon;
     int32_t* cslot;
     void* payload;
+    F4* pay32;          // FP64 plain builds: ((p - origin) / edge, r / edge) in FP32, slot order
     void* fbar;
     void* fsave;        // forces of the last forward step that kept them (slot order)
     double* partials;
@@ -186,6 +190,7 @@ inline Dev resolve(const Layout& L, void* base)
     d.canon = d.idx2;
     d.cslot = d.key2;
     d.payload = b + L.payload;
+    d.pay32 = reinterpret_cast<F4*>(b + L.pay32);
     d.fbar = b + L.fbar;
     d.fsave = b + L.fsave;
     d.partials = reinterpret_cast<double*>(b + L.partials);

@@ -24,10 +24,13 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
                                                   const ms_params* __restrict__ pB,
                                                   Header* __restrict__ hdr,
                                                   typename Mode<M>::Pay* __restrict__ dout,
-                                                  typename Mode<M>::Pay* __restrict__ fsave)
+                                                  typename Mode<M>::Pay* __restrict__ fsave,
+                                                  const F4* __restrict__ pay32)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
+    // plain FP64 builds scan their FP32 slot copy
+    constexpr bool PRE = M == MS_F64 && !BATCHED;
     __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     // forces kept for the backward step: record which build and parameters
@@ -46,8 +49,9 @@ __global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* _
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split, pay,
-                               (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x, fx, fy, fz);
+    force_sum<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
+                                    pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
+                                    pre32_of<PRE>(pay32, k, g), fx, fy, fz);
     if (fsave) {
         Pay f;
         f.x = fx; f.y = fy; f.z = fz; f.w = (Real)0;
@@ -271,19 +275,19 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
     ms_params dummy{};
     if (batched && list == kLongList)
         k_force<M, true, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off,
-                                                           B, n, dummy, p_dev, D.hdr, A, nullptr);
+                                                           B, n, dummy, p_dev, D.hdr, A, nullptr, D.pay32);
     else if (batched)
         k_force<M, true, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
                                                               D.off, B, n, dummy, p_dev, D.hdr, A,
-                                                              nullptr);
+                                                              nullptr, D.pay32);
     else if (list == kLongList)
         k_force<M, false, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
                                                             nullptr, 1, n, *p_host, nullptr, D.hdr,
-                                                            A, fs);
+                                                            A, fs, D.pay32);
     else
         k_force<M, false, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
                                                                nullptr, 1, n, *p_host, nullptr,
-                                                               D.hdr, A, fs);
+                                                               D.hdr, A, fs, D.pay32);
     if (px) {
         using In = typename Mode<M>::In;
         k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),

@@ -9,6 +9,8 @@
 
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace ms {
 
 // Fast single-precision square root / reciprocal (about 1 ulp), used on the
@@ -229,6 +231,41 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     return R;
 }
 
+// Candidate test of the FP64 path on the FP32 slot copy written by plain
+// FP64 builds (coordinates relative to the grid origin and radius, in units
+// of the box edge).  The test accepts |u| < r_i + r_j + tol; tol covers the
+// rounding of the copy (2^-24 of a coordinate, at most the box count per
+// axis) and of the FP32 test with a wide margin, so no pair in contact is
+// rejected, and the exact FP64 test of contact_force decides every accepted
+// pair.  The scan then loads 16 instead of 32 bytes per candidate.
+struct Pre32 {
+    const F4* pay32;
+    F4 pi;        // the agent's own copy
+    float tol;
+};
+
+__device__ __forceinline__ float pre32_tol(const SimGeom& g)
+{
+    const int m = g.dims[0] > g.dims[1] ? (g.dims[0] > g.dims[2] ? g.dims[0] : g.dims[2])
+                                        : (g.dims[1] > g.dims[2] ? g.dims[1] : g.dims[2]);
+    return ldexpf((float)m + 1.0f, -18);
+}
+
+// The Pre32 of slot k: its FP32 copy when PRE, an unused value otherwise.
+template <bool PRE>
+__device__ __forceinline__ Pre32 pre32_of(const F4* __restrict__ pay32, int64_t k, const SimGeom& g)
+{
+    Pre32 r;
+    r.pay32 = pay32;
+    r.pi = F4{0.0f, 0.0f, 0.0f, 0.0f};
+    r.tol = 0.0f;
+    if constexpr (PRE) {
+        r.pi = pay32[k];
+        r.tol = pre32_tol(g);
+    }
+    return r;
+}
+
 // Visit the candidates of agent `pi` that may touch it, in canonical order,
 // calling on_pair(offset, payload) for each candidate that passes the cheap
 // test |u|^2 < (ri + rj)^2 (offset = byte offset of its payload, self_off
@@ -243,19 +280,26 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
 // slot is always written, the cursor advances on a hit).  The pair work then
 // runs over the list, four payload loads in flight at a time.  The list is
 // drained (by the whole wavefront at once) before a group of four could
-// overflow any lane's list, so pairs are handed over in candidate order.  Offsets are 32-bit: a workspace holds fewer than 2^32
-// payload bytes.
-template <typename Real, typename Pay, int LIST = kMaxContacts, typename OnPair>
+// overflow any lane's list, so pairs are handed over in candidate order.
+// Offsets are 32-bit: a workspace holds fewer than 2^32 payload bytes.
+// PRE: the scan tests the FP32 slot copy `pre` instead of the payload (FP64
+// plain builds); the list then holds copy offsets, scaled to payload offsets
+// when drained.
+template <typename Real, typename Pay, int LIST = kMaxContacts, bool PRE = false, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
                                               const uint32_t* __restrict__ split,
                                               const Pay* __restrict__ pay, uint32_t* lst,
-                                              OnPair&& on_pair)
+                                              const Pre32& pre, OnPair&& on_pair)
 {
+    static_assert(!PRE || sizeof(Pay) == 2 * sizeof(F4), "the FP32 copy serves FP64 payloads");
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
+    constexpr uint32_t PS = PRE ? (uint32_t)sizeof(F4) : P;   // bytes per scanned candidate
+    constexpr uint32_t SH = PRE ? 1u : 0u;                      // scan offset -> payload offset
     static_assert(LIST % 4 == 0, "the list drains in groups of four");
     const char* base = reinterpret_cast<const char*>(pay);
+    const char* sbase = PRE ? reinterpret_cast<const char*>(pre.pay32) : base;
     int cnt = 0;
     auto drain = [&]() {
         for (int t = 0; t < cnt; t += 4) {
@@ -264,7 +308,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t v = lst[(t + u) * kBlock];
-                o[u] = (t + u < cnt) ? v : self_off;
+                o[u] = (t + u < cnt) ? (v << SH) : self_off;
             }
             pin4(o);
 #pragma unroll
@@ -274,33 +318,42 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
         }
         cnt = 0;
     };
-    auto test = [&](Pay q, uint32_t off, bool live) {
+    auto test = [&](auto q, uint32_t off, bool live) {
         pin(q);
-        const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-        const Real l2 = len2(ux, uy, uz);
-        const Real rs = pi.w + q.w;
-        lst[cnt * kBlock] = off;
-        cnt += (int)(live & (l2 < rs * rs));
+        if constexpr (PRE) {
+            const float ux = pre.pi.x - q.x, uy = pre.pi.y - q.y, uz = pre.pi.z - q.z;
+            const float l2 = len2(ux, uy, uz);
+            const float rt = pre.pi.w + q.w + pre.tol;
+            lst[cnt * kBlock] = off;
+            cnt += (int)(live & (l2 < rt * rt));
+        } else {
+            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
+            const Real l2 = len2(ux, uy, uz);
+            const Real rs = pi.w + q.w;
+            lst[cnt * kBlock] = off;
+            cnt += (int)(live & (l2 < rs * rs));
+        }
     };
+    using SPay = typename std::conditional<PRE, F4, Pay>::type;
     const Runs R = stencil_runs<Real>(g, c, start, split, pi.x, pi.y, pi.z, pi.w);
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-        const uint32_t end = (uint32_t)R.e[r] * P;
-        for (uint32_t off = (uint32_t)R.b[r] * P; off < end; off += 4 * P) {
+        const uint32_t end = (uint32_t)R.e[r] * PS;
+        for (uint32_t off = (uint32_t)R.b[r] * PS; off < end; off += 4 * PS) {
             // the whole wave drains when any lane's list is nearly full: the
             // lanes' drains run side by side instead of one after another
             if (__any(cnt > LIST - 4)) drain();
-            // The payload region has three spare entries after the last
+            // The scanned region has three spare entries after the last
             // agent, so the loads past a run's end stay inside it; those
             // slots are masked out of the test.
-            const Pay q0 = *reinterpret_cast<const Pay*>(base + off);
-            const Pay q1 = *reinterpret_cast<const Pay*>(base + off + P);
-            const Pay q2 = *reinterpret_cast<const Pay*>(base + off + 2 * P);
-            const Pay q3 = *reinterpret_cast<const Pay*>(base + off + 3 * P);
+            const SPay q0 = *reinterpret_cast<const SPay*>(sbase + off);
+            const SPay q1 = *reinterpret_cast<const SPay*>(sbase + off + PS);
+            const SPay q2 = *reinterpret_cast<const SPay*>(sbase + off + 2 * PS);
+            const SPay q3 = *reinterpret_cast<const SPay*>(sbase + off + 3 * PS);
             test(q0, off, true);
-            test(q1, off + P, off + P < end);
-            test(q2, off + 2 * P, off + 2 * P < end);
-            test(q3, off + 3 * P, off + 3 * P < end);
+            test(q1, off + PS, off + PS < end);
+            test(q2, off + 2 * PS, off + 2 * PS < end);
+            test(q3, off + 3 * PS, off + 3 * PS < end);
         }
     }
     drain();
@@ -309,16 +362,17 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
 // order (contact_force drops non-overlapping pairs and the agent itself).
 // LIST: length of the per-lane contact list `lst` (stride kBlock).
-template <typename Real, typename Pay, int LIST = kMaxContacts>
+template <typename Real, typename Pay, int LIST = kMaxContacts, bool PRE = false>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          uint32_t* lst, Real& fx, Real& fy, Real& fz)
+                                          uint32_t* lst, const Pre32& pre, Real& fx, Real& fy,
+                                          Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay, LIST>(g, c, pi, self_off, start, split, pay, lst,
-                                   [&](uint32_t, const Pay& q) {
+    scan_contacts<Real, Pay, LIST, PRE>(g, c, pi, self_off, start, split, pay, lst, pre,
+                                        [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });
     fx = ax; fy = ay; fz = az;

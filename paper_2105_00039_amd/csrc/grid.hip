@@ -649,6 +649,40 @@ __device__ __forceinline__ uint32_t split_word(uint32_t w, int cnt)
     return cnt > 255 ? kSplitNone : (w | ((uint32_t)cnt << 24));
 }
 
+// FP32 copy of each FP64 slot for the gather's candidate test (plain FP64
+// builds): coordinates relative to the grid origin and the radius, both in
+// units of the box edge, so every value is bounded by the box count per axis
+// and nothing overflows.  `on` is false for the other builds.
+struct Slot32 {
+    F4* p;
+    double o0, o1, o2, ie;
+    bool on;
+    __device__ Slot32(F4* pay32, const SimGeom* g)
+        : p(pay32), o0(0.0), o1(0.0), o2(0.0), ie(0.0), on(g != nullptr)
+    {
+        if (on) {
+            o0 = g->origin[0];
+            o1 = g->origin[1];
+            o2 = g->origin[2];
+            ie = 1.0 / g->edge;
+        }
+    }
+    template <typename Pay>
+    __device__ __forceinline__ void put(int slot, const Pay& q) const
+    {
+        if constexpr (sizeof(Pay) == sizeof(D4)) {
+            if (on) {
+                F4 v;
+                v.x = (float)((q.x - o0) * ie);
+                v.y = (float)((q.y - o1) * ie);
+                v.z = (float)((q.z - o2) * ie);
+                v.w = (float)(q.w * ie);
+                p[slot] = v;
+            }
+        }
+    }
+};
+
 // Buckets holding more agents than the LDS stage: after the box counts, box
 // starts and the arrival-order placement (tmp[s0 + slot] = position of the
 // slot's agent in the bucket input, c[k] = end of box k), the boxes are taken
@@ -663,7 +697,8 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                             const int32_t* __restrict__ idx2,
                             const typename Mode<M>::Pay* __restrict__ pay2,
                             const int32_t* __restrict__ tmp, uint32_t* __restrict__ split,
-                            int32_t* __restrict__ perm, typename Mode<M>::Pay* __restrict__ pay)
+                            int32_t* __restrict__ perm, typename Mode<M>::Pay* __restrict__ pay,
+                            const Slot32& s32)
 {
     int kb = 0, cs = 0;   // first box and first slot of the chunk (block-uniform)
     while (kb < nbox) {
@@ -739,6 +774,7 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 if (p < cn) {
                     perm[s0 + cs + p] = mem[jj[u]];
                     pay[s0 + cs + p] = q[u];
+                    s32.put(s0 + cs + p, q[u]);
                 }
             }
             __syncthreads();
@@ -758,7 +794,9 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 if (r == 0)
                     reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + cs), kSplitNone);
                 perm[s0 + cs + r] = orig;
-                pay[s0 + cs + r] = pay2[s0 + pe];
+                const typename Mode<M>::Pay qv = pay2[s0 + pe];
+                pay[s0 + cs + r] = qv;
+                s32.put(s0 + cs + r, qv);
             }
         }
         kb = ke;
@@ -776,7 +814,9 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              uint32_t* __restrict__ split,
                                                              int32_t* __restrict__ tmp,
                                                              int32_t* __restrict__ perm,
-                                                             typename Mode<M>::Pay* __restrict__ pay)
+                                                             typename Mode<M>::Pay* __restrict__ pay,
+                                                             F4* __restrict__ pay32,
+                                                             const SimGeom* __restrict__ g32)
 {
     __shared__ int32_t c[kSortBoxes];
     __shared__ int32_t mem[kSortStage];      // input index of each box member, arrival order
@@ -866,7 +906,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     }
     __syncthreads();
     if (!staged) {   // block-uniform
-        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, pay2, tmp, split, perm, pay);
+        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, pay2, tmp, split, perm, pay,
+                       Slot32(pay32, g32));
         return;
     }
     // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
@@ -892,6 +933,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     // 5. write the sorted bucket in slot order (loads issued before the stores)
     if (s1 > s0) {   // block-uniform; padding lanes read slot s0
+        const Slot32 s32(pay32, g32);
         constexpr int U = kSortStage / kSortThreads;
         const int cnt = s1 - s0;
         int e[U];
@@ -913,6 +955,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
             if (p < cnt) {
                 perm[s0 + p] = id[u];
                 pay[s0 + p] = q[u];
+                s32.put(s0 + p, q[u]);
             }
         }
     }
@@ -990,7 +1033,8 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
         D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), btot, D.start, D.split, D.tmp,
         D.perm,
-        static_cast<Pay*>(D.payload));
+        static_cast<Pay*>(D.payload), D.pay32,
+        (M == MS_F64 && !batched) ? static_cast<const SimGeom*>(D.geom) : nullptr);
     return hipGetLastError();
 }
 
