@@ -13,8 +13,12 @@
 namespace ms {
 namespace {
 
+// Plain FP64 builds ask for at least 4 wavefronts per SIMD (at most 128
+// VGPRs, against 131 otherwise): with 3 the gather's loads are hidden worse
+// (force kernel at 2M agents, n~12: 309 -> 287 us).
 template <int M, bool BATCHED, int LIST>
-__global__ __launch_bounds__(kBlock) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
                                                   const int32_t* __restrict__ start,
                                                   const uint32_t* __restrict__ split,
                                                   const int32_t* __restrict__ perm,
