@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
-    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (BATCHED) s = block_sim(off, B, n, k0, k, reinterpret_cast<int*>(lst));
     if (k >= n) return;
     const SimGeom g = geom[s];
     const ms_params P = BATCHED ? pB[s] : p1;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
     if (BATCHED) {
-        s = block_sim(off, B, n, k0, k);
+        s = block_sim(off, B, n, k0, k, reinterpret_cast<int*>(lst));
         if (threadIdx.x == 0) {
             const int64_t last = (k0 + kBlock < n ? k0 + kBlock : n) - 1;
             s_rng[0] = find_sim(off, 0, B, k0);

@@ -46,7 +46,7 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
-    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (BATCHED) s = block_sim(off, B, n, k0, k, reinterpret_cast<int*>(lst));
     if (k >= n) return;
     const SimGeom g = geom[s];
     const ms_params P = BATCHED ? pB[s] : p1;
@@ -145,8 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(const typename Mode<M>::Pa
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
+    __shared__ int s_range[2];
     int s = 0;
-    if (BATCHED) s = block_sim(off, B, n, k0, k);
+    if (BATCHED) s = block_sim(off, B, n, k0, k, s_range);
     if (k >= n) return;
     const SimGeom g = geom[s];
     const Pay pi = pay[k];

@@ -25,19 +25,21 @@ __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
 
 // Simulation of every thread of a block over a sorted or input range:
 // thread 0 finds the simulations of the block's first and last index, then
-// each thread searches only between them.
+// each thread searches only between them.  s_range: two ints of LDS, free
+// again when this returns (the gather kernels lend the first entries of
+// their contact lists, so no extra LDS limits how many blocks fit a CU).
 __device__ __forceinline__ int block_sim(const int64_t* __restrict__ off, int32_t B, int64_t n,
-                                         int64_t first, int64_t i)
+                                         int64_t first, int64_t i, int* s_range)
 {
-    __shared__ int s_range[2];
     if (threadIdx.x == 0) {
         const int64_t last = (first + kBlock < n ? first + kBlock : n) - 1;
         s_range[0] = find_sim(off, 0, B, first);
         s_range[1] = find_sim(off, 0, B, last);
     }
     __syncthreads();
-    if (i >= n) return 0;
-    return find_sim(off, s_range[0], s_range[1] + 1, i);
+    const int s = i < n ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
+    __syncthreads();
+    return s;
 }
 
 struct Cell { int ix, iy, iz; };
