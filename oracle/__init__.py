@@ -19,6 +19,8 @@ Functions and the passages they follow:
 * ``sample``                       ``step`` and ``tolerance_scales`` for a
                                    sample of agents of a large population.
 * ``step_adjoint``                 reverse-mode derivative of ``step``.
+* ``adjoint_scales``               per-agent scales of the acceptance test
+                                   for gradients.
 * ``rollout``, ``rollout_grad``    repeated steps with the grid rebuilt each
                                    step (Section IV-A) and their gradient.
 """
@@ -34,11 +36,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mech_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+# The timing copy for the CPU baseline: same source, -O3 for the host it is
+# built on.  It is compiled where it runs, never shipped prebuilt.
+_LIB_FAST = os.path.join(_HERE, "liborc_native.so")
 # A test may point the wrapper at another build of the oracle (the mutation
 # tests load deliberately broken copies to show the pins catch them).
 _LIB_OVERRIDE = os.environ.get("ORACLE_LIB_OVERRIDE")
 _CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-Wextra", "-Wno-unused-parameter"]
+           "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+_CFLAGS_FAST = ["-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                "-fno-fast-math", "-fopenmp"]
 _lock = threading.Lock()
 _lib = None
 
@@ -51,13 +58,26 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def build(force: bool = False) -> str:
-    """Compile liborc.so with gcc (portable x86-64, no -march=native)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile liborc.so with gcc (portable x86-64, OpenMP), or with
+    native=True the timing copy liborc_native.so (-O3 -march=native, OpenMP;
+    always recompiled, for the host it runs on)."""
+    out, flags = (_LIB_FAST, _CFLAGS_FAST) if native else (_LIB, _CFLAGS)
+    if native or force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", *flags, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
+
+
+def use_native():
+    """Load the -O3 -march=native timing copy in place of the test build
+    (before the first call; the CPU baseline of the benchmark uses it)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            raise RuntimeError("oracle already loaded")
+        _lib = _bind(ctypes.CDLL(build(native=True)))
 
 
 def lib():
@@ -69,27 +89,39 @@ def lib():
             else:
                 build()
                 L = ctypes.CDLL(_LIB)
-            P = ctypes.c_void_p
-            I64 = ctypes.c_int64
-            D = ctypes.c_double
-            sig = {
-                "orc_geometry": [I64, P, P, P, P, D, P, P, P, P],
-                "orc_grid": [I64, P, P, P, P, D, P, P, P],
-                "orc_neighbors": [I64, P, P, P, P, D, P, P, P, I64],
-                "orc_brute_neighbors": [I64, P, P, P, D, P, P, P, I64],
-                "orc_step": [I64, P, P, P, P, D, P, P, P, P, P, P, P],
-                "orc_brute_forces": [I64, P, P, P, P, D, D, P, P, P],
-                "orc_tolerance_scales": [I64, P, P, P, P, D, D, D, D, P, P, P],
-                "orc_step_adjoint": [I64, P, P, P, P, D, P, P, P, P, P, P, P, P, P],
-                "orc_integrate": [I64, P, P, P, P, P, P],
-                "orc_sample": [I64, P, P, P, P, D, P, D, I64, P, P, P, P, P, P, P, P, P, P],
-            }
-            for name, args in sig.items():
-                f = getattr(L, name)
-                f.argtypes = args
-                f.restype = ctypes.c_int
-            _lib = L
+            _lib = _bind(L)
     return _lib
+
+
+def _bind(L):
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    sig = {
+        "orc_geometry": [I64, P, P, P, P, D, P, P, P, P],
+        "orc_grid": [I64, P, P, P, P, D, P, P, P],
+        "orc_neighbors": [I64, P, P, P, P, D, P, P, P, I64],
+        "orc_brute_neighbors": [I64, P, P, P, D, P, P, P, I64],
+        "orc_step": [I64, P, P, P, P, D, P, P, P, P, P, P, P],
+        "orc_brute_forces": [I64, P, P, P, P, D, D, P, P, P],
+        "orc_tolerance_scales": [I64, P, P, P, P, D, D, D, D, P, P, P],
+        "orc_step_adjoint": [I64, P, P, P, P, D, P, P, P, P, P, P, P, P, P],
+        "orc_integrate": [I64, P, P, P, P, P, P],
+        "orc_sample": [I64, P, P, P, P, D, P, D, I64, P, P, P, P, P, P, P, P, P, P],
+        "orc_adjoint_scales": [I64, P, P, P, P, D, P, P, P, P, D, P, P, P, P, P],
+        "orc_set_threads": [ctypes.c_int],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    return L
+
+
+def set_threads(t: int) -> int:
+    """Threads for the following calls (t <= 0 leaves it); returns the count.
+    Results do not depend on it."""
+    return int(lib().orc_set_threads(int(t)))
 
 
 def _f64(a):
@@ -227,6 +259,24 @@ def step_adjoint(x, y, z, d, params, gD, edge=0.0):
     _check(lib().orc_step_adjoint(n, _p(x), _p(y), _p(z), _p(d), float(edge), _p(_params(params)),
                                   *map(_p, g), *map(_p, gp), _p(gd), _p(gkg)), "step_adjoint")
     return np.stack(gp, axis=1), gd, gkg
+
+
+def adjoint_scales(x, y, z, d, params, gD, unit_roundoff, edge=0.0):
+    """Per-agent scales of the gradient acceptance test for gD = dL/dDelta:
+    (Sp, Ap) for the position gradient, (Sd, Ad) for the diameter gradient,
+    and [S_kappa, A_kappa, S_gamma, A_gamma] for the parameter gradients (see
+    mech_oracle.c).  A gradient g of the same step computed in another
+    precision or order is accepted when |g_i - g_oracle_i| <= tau S_i + A_i."""
+    x, y, z, d = map(_f64, (x, y, z, d))
+    n = x.size
+    gD = np.asarray(gD, dtype=np.float64)
+    g = [np.ascontiguousarray(gD[:, k]) for k in range(3)]
+    out = [np.zeros(n) for _ in range(4)]
+    skg = np.zeros(4)
+    _check(lib().orc_adjoint_scales(n, _p(x), _p(y), _p(z), _p(d), float(edge), _p(_params(params)),
+                                    *map(_p, g), float(unit_roundoff), *map(_p, out), _p(skg)),
+           "adjoint_scales")
+    return out[0], out[1], out[2], out[3], skg
 
 
 def rollout(x, y, z, d, params, steps, edge=0.0):

@@ -41,6 +41,11 @@
  *   - the exported neighbour set uses the predicate |p_i - p_j|^2 < e^2 with
  *     |u|^2 = (ux*ux + uy*uy) + uz*uz in FP64.
  *
+ * Threads: built with OpenMP, the per-agent loops are split over threads.
+ * Every agent's own sums stay sequential in canonical order and the global
+ * sums (dL/dkappa, dL/dgamma) add per-agent partials in agent order, so the
+ * results are identical bit for bit for any thread count.
+ *
  * Status codes (same numbering as the product boundary so tests can compare
  * error behaviour): 0 ok, 1 invalid argument, 2 capacity, 4 invalid input
  * values (non-finite position/diameter or negative diameter).
@@ -49,6 +54,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL 1
@@ -258,18 +266,20 @@ int orc_neighbors(int64_t n, const double *x, const double *y, const double *z,
     orc_grid_t G;
     int st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
     if (st) { grid_free(&G); return st; }
-    nb_ctx C = {x, y, z, G.g.edge * G.g.edge, 0, NULL};
-    offsets[0] = 0;
+    const double e2 = G.g.edge * G.g.edge;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        C.count = 0; C.out = NULL;
+        nb_ctx C = {x, y, z, e2, 0, NULL};
         visit_candidates(&G, x, y, z, i, nb_visit, &C);
         counts[i] = (int32_t)C.count;
-        offsets[i + 1] = offsets[i] + C.count;
     }
+    offsets[0] = 0;
+    for (int64_t i = 0; i < n; ++i) offsets[i + 1] = offsets[i] + counts[i];
     if (list) {
         if (cap < offsets[n]) { grid_free(&G); return ORC_ECAPACITY; }
+#pragma omp parallel for schedule(dynamic, 256)
         for (int64_t i = 0; i < n; ++i) {
-            C.count = 0; C.out = list + offsets[i];
+            nb_ctx C = {x, y, z, e2, 0, list + offsets[i]};
             visit_candidates(&G, x, y, z, i, nb_visit, &C);
         }
     }
@@ -373,9 +383,9 @@ int orc_step(int64_t n, const double *x, const double *y, const double *z, const
     orc_grid_t G;
     st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
     if (st) { grid_free(&G); return st; }
-    force_ctx C = {x, y, z, d, params[0], params[1], {0, 0, 0}};
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        C.f[0] = C.f[1] = C.f[2] = 0.0;
+        force_ctx C = {x, y, z, d, params[0], params[1], {0, 0, 0}};
         visit_candidates(&G, x, y, z, i, force_visit, &C);
         double D[3];
         displacement(C.f, params[2], params[3], params[4], D);
@@ -448,9 +458,9 @@ int orc_tolerance_scales(int64_t n, const double *x, const double *y, const doub
     orc_grid_t G;
     int st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
     if (st) { grid_free(&G); return st; }
-    tol_ctx T = {x, y, z, d, kappa, gamma, u, 0, 0, 0};
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        T.S = T.A = 0.0; T.contacts = 0;
+        tol_ctx T = {x, y, z, d, kappa, gamma, u, 0, 0, 0};
         visit_candidates(&G, x, y, z, i, tol_visit, &T);
         S[i] = T.S; A[i] = T.A;
         if (C) C[i] = (int32_t)T.contacts;
@@ -480,18 +490,17 @@ int orc_sample(int64_t n, const double *x, const double *y, const double *z, con
     orc_grid_t G;
     st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
     if (st) { grid_free(&G); return st; }
-    force_ctx F = {x, y, z, d, params[0], params[1], {0, 0, 0}};
-    tol_ctx T = {x, y, z, d, params[0], params[1], u, 0, 0, 0};
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < m; ++k) {
         const int64_t i = idx[k];
-        F.f[0] = F.f[1] = F.f[2] = 0.0;
+        force_ctx F = {x, y, z, d, params[0], params[1], {0, 0, 0}};
+        tol_ctx T = {x, y, z, d, params[0], params[1], u, 0, 0, 0};
         visit_candidates(&G, x, y, z, i, force_visit, &F);
         double D[3];
         displacement(F.f, params[2], params[3], params[4], D);
         if (fx) { fx[k] = F.f[0]; fy[k] = F.f[1]; fz[k] = F.f[2]; }
         if (dx) { dx[k] = D[0]; dy[k] = D[1]; dz[k] = D[2]; }
         if (S || A || C) {
-            T.S = T.A = 0.0; T.contacts = 0;
             visit_candidates(&G, x, y, z, i, tol_visit, &T);
             if (S) S[k] = T.S;
             if (A) A[k] = T.A;
@@ -571,26 +580,19 @@ static void adj_visit(void *c, int64_t i, int64_t j)
     C->gb += -sq * eF;
 }
 
-int orc_step_adjoint(int64_t n, const double *x, const double *y, const double *z,
-                     const double *d, double edge_in, const double *params,
-                     const double *gdx, const double *gdy, const double *gdz,
-                     double *gx, double *gy, double *gz, double *gd, double *gkg)
+/* Step 1 of the adjoint for every agent: the total force (canonical order)
+ * pulled back through the displacement rule into Fb [3n]. */
+static void fbar_all(const orc_grid_t *G, int64_t n, const double *x, const double *y,
+                     const double *z, const double *d, const double *params,
+                     const double *gdx, const double *gdy, const double *gdz, double *Fb)
 {
-    int st = check_params(params);
-    if (st) return st;
-    orc_grid_t G;
-    st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
-    if (st) { grid_free(&G); return st; }
     double dt = params[2], m = params[3], a = params[4];
-    double *Fb = (double *)calloc((size_t)(n > 0 ? 3 * n : 1), sizeof(double));
-    if (!Fb) { grid_free(&G); return ORC_EINVAL; }
-    adj_ctx C;
-    memset(&C, 0, sizeof(C));
-    C.x = x; C.y = y; C.z = z; C.d = d; C.kappa = params[0]; C.gamma = params[1]; C.Fb = Fb;
-    /* step 1 */
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        C.f[0] = C.f[1] = C.f[2] = 0.0;
-        visit_candidates(&G, x, y, z, i, adj_force_visit, &C);
+        adj_ctx C;
+        memset(&C, 0, sizeof(C));
+        C.x = x; C.y = y; C.z = z; C.d = d; C.kappa = params[0]; C.gamma = params[1];
+        visit_candidates(G, x, y, z, i, adj_force_visit, &C);
         double g[3] = {gdx[i], gdy[i], gdz[i]};
         double fn = sqrt(dist2(C.f[0], C.f[1], C.f[2]));
         double *o = Fb + 3 * i;
@@ -606,19 +608,150 @@ int orc_step_adjoint(int64_t n, const double *x, const double *y, const double *
             for (int k = 0; k < 3; ++k) o[k] = dt * g[k];
         }
     }
-    /* step 2 */
-    double kb = 0.0, gb = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        C.pb[0] = C.pb[1] = C.pb[2] = 0.0; C.rb = 0.0; C.kb = 0.0; C.gb = 0.0;
+}
+
+int orc_step_adjoint(int64_t n, const double *x, const double *y, const double *z,
+                     const double *d, double edge_in, const double *params,
+                     const double *gdx, const double *gdy, const double *gdz,
+                     double *gx, double *gy, double *gz, double *gd, double *gkg)
+{
+    int st = check_params(params);
+    if (st) return st;
+    orc_grid_t G;
+    st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
+    if (st) { grid_free(&G); return st; }
+    double *Fb = (double *)calloc((size_t)(n > 0 ? 3 * n : 1), sizeof(double));
+    double *kg = (double *)calloc((size_t)(n > 0 ? 2 * n : 1), sizeof(double));
+    if (!Fb || !kg) { free(Fb); free(kg); grid_free(&G); return ORC_EINVAL; }
+    fbar_all(&G, n, x, y, z, d, params, gdx, gdy, gdz, Fb);      /* step 1 */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {                             /* step 2 */
+        adj_ctx C;
+        memset(&C, 0, sizeof(C));
+        C.x = x; C.y = y; C.z = z; C.d = d; C.kappa = params[0]; C.gamma = params[1]; C.Fb = Fb;
         visit_candidates(&G, x, y, z, i, adj_visit, &C);
         gx[i] = C.pb[0]; gy[i] = C.pb[1]; gz[i] = C.pb[2];
         gd[i] = 0.5 * C.rb;
-        kb += C.kb; gb += C.gb;
+        kg[2 * i] = C.kb; kg[2 * i + 1] = C.gb;
     }
+    double kb = 0.0, gb = 0.0;
+    for (int64_t i = 0; i < n; ++i) { kb += kg[2 * i]; gb += kg[2 * i + 1]; }
     gkg[0] = kb; gkg[1] = gb;
     free(Fb);
+    free(kg);
     grid_free(&G);
     return ORC_OK;
+}
+
+/* ------------------------------------------------ gradient tolerance scales --- */
+/*
+ * Per-agent scales of the acceptance test used when comparing a gradient
+ * computed in another precision or summation order with orc_step_adjoint.
+ * Every term of the adjoint gather is linear in w = Fbar_i - Fbar_j with
+ * coefficients built from s, ds/ddelta and ds/drho, so, with
+ * W = |Fbar_i| + |Fbar_j| (which bounds |w| and |q| = |e . w| and cannot
+ * cancel), summed over the contacts of agent i:
+ *   Sp[i] = sum W (2|s|/l + |s_delta|)
+ *           bounds |pbar_i| term by term: |(s/l)(w - e q)| <= (|s|/l)(|w| + |q|)
+ *           and |s_delta q e| <= |s_delta| W;
+ *   Sd[i] = sum W (|s_delta| + |s_rho| r_j^2/(r_i + r_j)^2) / 2, the same for dbar_i;
+ *   Ap[i], Ad[i]: what rounding the overlap by eta = 4u(r_i + r_j + l) can
+ *           change in them, eta times the derivatives in delta of the
+ *           coefficients:
+ *           Ap: sum eta W (2|s_delta|/l + s_dd),
+ *           Ad: sum eta W (s_dd + gamma/(4 sqrt(rho dm)) r_j^2/(r_i + r_j)^2) / 2,
+ *           s_dd = gamma rho^2 / (4 (rho dm)^(3/2)) = d s_delta / d delta,
+ *           dm = max(delta, eta);
+ *   skg[0..3] = {sum |delta| |Fbar_i|, sum eta |Fbar_i|,
+ *                sum sqrt(rho delta) |Fbar_i|, sum eta rho/(2 sqrt(rho dm)) |Fbar_i|}
+ *           over all ordered contact pairs: the scale and allowance of
+ *           dL/dkappa, then of dL/dgamma.
+ * Fbar is step 1 of orc_step_adjoint for the same gbar.  u is the unit
+ * roundoff of the compared precision.
+ */
+typedef struct {
+    const double *x, *y, *z, *d, *Fb;
+    double kappa, gamma, u;
+    double Sp, Ap, Sd, Ad, sk[4];
+} adjtol_ctx;
+
+static double norm3(const double *v) { return sqrt(dist2(v[0], v[1], v[2])); }
+
+static void adjtol_visit(void *c, int64_t i, int64_t j)
+{
+    adjtol_ctx *C = (adjtol_ctx *)c;
+    double ri = 0.5 * C->d[i], rj = 0.5 * C->d[j];
+    double ux = C->x[i] - C->x[j], uy = C->y[i] - C->y[j], uz = C->z[i] - C->z[j];
+    double l = sqrt(dist2(ux, uy, uz));
+    double delta = (ri + rj) - l;
+    if (!(delta > 0.0) || !(l > 0.0)) return;
+    double rs = ri + rj;
+    double rho = (ri * rj) / rs;
+    double sq = sqrt(rho * delta);
+    const double s = C->kappa * delta - C->gamma * sq;
+    const double s_delta = C->kappa - C->gamma * rho / (2.0 * sq);
+    const double s_rho = -(C->gamma * delta) / (2.0 * sq);
+    const double eta = 4.0 * C->u * (ri + rj + l);
+    double dm = delta > eta ? delta : eta;
+    double sqm = sqrt(rho * dm);
+    double s_dd = C->gamma * rho * rho / (4.0 * sqm * sqm * sqm);
+    double c2 = (rj * rj) / (rs * rs);
+    double fi = norm3(C->Fb + 3 * i), fj = norm3(C->Fb + 3 * j);
+    double W = fi + fj;
+    C->Sp += W * (2.0 * fabs(s) / l + fabs(s_delta));
+    C->Ap += eta * W * (2.0 * fabs(s_delta) / l + s_dd);
+    C->Sd += 0.5 * W * (fabs(s_delta) + fabs(s_rho) * c2);
+    C->Ad += 0.5 * eta * W * (s_dd + C->gamma / (4.0 * sqm) * c2);
+    C->sk[0] += delta * fi;
+    C->sk[1] += eta * fi;
+    C->sk[2] += sq * fi;
+    C->sk[3] += eta * rho / (2.0 * sqm) * fi;
+}
+
+int orc_adjoint_scales(int64_t n, const double *x, const double *y, const double *z,
+                       const double *d, double edge_in, const double *params,
+                       const double *gdx, const double *gdy, const double *gdz, double u,
+                       double *Sp, double *Ap, double *Sd, double *Ad, double *skg)
+{
+    int st = check_params(params);
+    if (st) return st;
+    orc_grid_t G;
+    st = grid_alloc_build(n, x, y, z, d, edge_in, &G);
+    if (st) { grid_free(&G); return st; }
+    double *Fb = (double *)calloc((size_t)(n > 0 ? 3 * n : 1), sizeof(double));
+    double *sk = (double *)calloc((size_t)(n > 0 ? 4 * n : 1), sizeof(double));
+    if (!Fb || !sk) { free(Fb); free(sk); grid_free(&G); return ORC_EINVAL; }
+    fbar_all(&G, n, x, y, z, d, params, gdx, gdy, gdz, Fb);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        adjtol_ctx C;
+        memset(&C, 0, sizeof(C));
+        C.x = x; C.y = y; C.z = z; C.d = d; C.Fb = Fb;
+        C.kappa = params[0]; C.gamma = params[1]; C.u = u;
+        visit_candidates(&G, x, y, z, i, adjtol_visit, &C);
+        Sp[i] = C.Sp; Ap[i] = C.Ap; Sd[i] = C.Sd; Ad[i] = C.Ad;
+        for (int k = 0; k < 4; ++k) sk[4 * i + k] = C.sk[k];
+    }
+    for (int k = 0; k < 4; ++k) skg[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 4; ++k) skg[k] += sk[4 * i + k];
+    free(Fb);
+    free(sk);
+    grid_free(&G);
+    return ORC_OK;
+}
+
+/* Threads of the OpenMP build for the calls that follow (ignored without
+ * OpenMP); returns the number in use. */
+int orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+    return omp_get_max_threads();
+#else
+    (void)t;
+    return 1;
+#endif
 }
 
 /* p <- p + Delta for every agent at once (Jacobi update). */

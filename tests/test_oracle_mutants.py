@@ -2,7 +2,8 @@
 
 Each case copies the oracle source, plants one mistake by replacing one line
 (a flipped sign, a dropped division, a missing stencil plane, ...), builds the
-copy with gcc and runs the pin tests against it in a subprocess.  The pins
+copy with gcc and the oracle's own flags, and runs the pin tests against it in
+a subprocess.  The pins
 must fail for every mutant.  Nothing here touches the GPU path.
 """
 import os
@@ -35,6 +36,19 @@ MUTANTS = {
                           "double s_rho = C->gamma * delta / (2.0 * sq);"),
     "adjoint_drop_sdelta": ("C->pb[k] += (s / l) * (w[k] - e[k] * q) - s_delta * q * e[k];",
                             "C->pb[k] += (s / l) * (w[k] - e[k] * q);"),
+    # acceptance-test scales: an allowance or scale that is too large must be
+    # caught as well as one that is too small
+    "tol_drop_onset_guard": ("    if (delta > -eta) {\n        double dm = delta > eta ? delta : eta;",
+                             "    if (1) {\n        double dm = delta > eta ? delta : eta;"),
+    "tol_eta_x16": ("    double eta = 4.0 * C->u * (ri + rj + l);\n    if (delta > 0.0 && l > 0.0) {",
+                    "    double eta = 64.0 * C->u * (ri + rj + l);\n    if (delta > 0.0 && l > 0.0) {"),
+    "tol_S_sign": ("C->S += C->kappa * delta + C->gamma * sqrt(rho * delta);",
+                   "C->S += C->kappa * delta - C->gamma * sqrt(rho * delta);"),
+    "adjtol_drop_fj": ("double W = fi + fj;", "double W = fi;"),
+    "adjtol_drop_sdelta": ("C->Sp += W * (2.0 * fabs(s) / l + fabs(s_delta));",
+                           "C->Sp += W * (2.0 * fabs(s) / l);"),
+    "adjtol_eta_x16": ("    const double eta = 4.0 * C->u * (ri + rj + l);",
+                       "    const double eta = 64.0 * C->u * (ri + rj + l);"),
     "adjoint_clamp_projection": ("for (int k = 0; k < 3; ++k) o[k] = sc * (g[k] - vh[k] * vg);",
                                  "for (int k = 0; k < 3; ++k) o[k] = sc * g[k];"),
 }
@@ -48,8 +62,8 @@ def test_pins_catch_mutant(name, tmp_path):
     mutant_c = tmp_path / "mutant.c"
     mutant_c.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                    "-o", str(lib), str(mutant_c), "-lm"], check=True)
+    import oracle
+    subprocess.run(["gcc", *oracle._CFLAGS, "-o", str(lib), str(mutant_c), "-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)

@@ -327,3 +327,132 @@ def test_sample_equals_full_step_rows(pop):
     assert np.array_equal(Ss, S[idx]) and np.array_equal(As, A[idx]) and np.array_equal(Cs, C[idx])
     with pytest.raises(oracle.OracleError):
         oracle.sample(*arrs, prm, np.array([pop.n]))
+
+
+# ------------------------------------------------ acceptance-test scales ---
+#
+# oracle.tolerance_scales supplies S (magnitude of an agent's contact terms)
+# and A (the contact-onset allowance) for every GPU parity bound tau*S + A.
+# These pins fix both to closed forms of Eq. 1 on hand-worked pairs, so a
+# scale that is too large is caught as well as one that is too small.
+
+U24 = 2.0 ** -24
+
+
+def _scales(x2, d1=10.0, d2=10.0, u=U24, kappa=2.0, gamma=1.0):
+    return oracle.tolerance_scales(*pair(x2, d1, d2), kappa, gamma, u)
+
+
+def test_tolerance_scales_closed_forms():
+    # W1: delta = 1, rho = 2.5, l = 9; eta = 4u(r1 + r2 + l) = 76u
+    S, A, C = _scales(9.0)
+    eta = 4 * U24 * 19.0
+    assert list(C) == [1, 1]
+    np.testing.assert_allclose(S, 2.0 + np.sqrt(2.5), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(A, (2.0 + np.sqrt(2.5) / 2.0) * eta, rtol=1e-14, atol=0)
+    # W5: radii 4 and 6, delta = 1, rho = 2.4, l = 9
+    S, A, C = _scales(9.0, 8.0, 12.0)
+    np.testing.assert_allclose(S, 2.0 + np.sqrt(2.4), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(A, (2.0 + np.sqrt(2.4) / 2.0) * eta, rtol=1e-14, atol=0)
+    # coefficients enter linearly: kappa = 3, gamma = 0.5
+    S, A, _ = _scales(9.0, kappa=3.0, gamma=0.5)
+    np.testing.assert_allclose(S, 3.0 + 0.5 * np.sqrt(2.5), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(A, (3.0 + 0.5 * np.sqrt(2.5) / 2.0) * eta, rtol=1e-14, atol=0)
+    # W3b, apart by 0.5 >> eta: no contact, no allowance
+    S, A, C = _scales(10.5)
+    assert np.all(S == 0) and np.all(A == 0) and np.all(C == 0)
+    # W3a, touching (delta = 0 > -eta): no contact, but rounding could make
+    # one: A = (kappa + gamma sqrt(rho)/(2 sqrt(eta))) eta, eta = 4u * 20
+    S, A, C = _scales(10.0)
+    eta = 4 * U24 * 20.0
+    assert np.all(S == 0) and np.all(C == 0)
+    np.testing.assert_allclose(A, (2.0 + np.sqrt(2.5) / (2.0 * np.sqrt(eta))) * eta, rtol=1e-14)
+    # just apart, inside the onset band (-eta < delta < 0)
+    x2 = 10.0 + 2e-6
+    S, A, C = _scales(x2)
+    eta = 4 * U24 * (10.0 + x2)
+    assert 2e-6 < eta and np.all(S == 0)
+    np.testing.assert_allclose(A, (2.0 + np.sqrt(2.5) / (2.0 * np.sqrt(eta))) * eta, rtol=1e-9)
+    # just apart, outside the band: nothing
+    S, A, C = _scales(10.0 + 1e-4)
+    assert np.all(S == 0) and np.all(A == 0)
+    # coincident centres (W7): never a contact; the allowance counts the pair
+    # as an onset pair at l = 0 (delta = 10 > eta)
+    S, A, C = oracle.tolerance_scales(np.zeros(2), np.zeros(2), np.zeros(2), np.array([10.0, 10.0]),
+                                      2.0, 1.0, U24)
+    assert np.all(S == 0) and np.all(C == 0)
+    np.testing.assert_allclose(A, (2.0 + np.sqrt(2.5) / (2.0 * np.sqrt(10.0))) * 4 * U24 * 10.0,
+                               rtol=1e-14)
+
+
+def test_tolerance_scales_add_over_contacts():
+    # three agents on a line, 9 apart: the middle one has two W1 contacts,
+    # the end ones one each; the ends are 18 apart (no contact, no allowance)
+    x = np.array([0.0, 9.0, 18.0])
+    S, A, C = oracle.tolerance_scales(x, np.zeros(3), np.zeros(3), np.full(3, 10.0), 2.0, 1.0, U24)
+    s1 = 2.0 + np.sqrt(2.5)
+    a1 = (2.0 + np.sqrt(2.5) / 2.0) * 4 * U24 * 19.0
+    np.testing.assert_allclose(S, [s1, 2 * s1, s1], rtol=1e-15)
+    np.testing.assert_allclose(A, [a1, 2 * a1, a1], rtol=1e-14)
+    assert list(C) == [1, 2, 1]
+
+
+@pytest.mark.parametrize("u", [2.0 ** -24, 2.0 ** -53, 1e-3])
+def test_tolerance_scales_match_all_pairs(u):
+    """S, A, C recomputed over every pair (no grid) in numpy: the oracle's
+    sums over the 27-box candidates miss no pair with delta > -eta and take
+    in no other."""
+    pop = workloads.uniform(500, mean_neighbors=25.0, seed=31)
+    x, y, z, d = pop.arrays()
+    kappa, gamma = 1.6, 0.7
+    S, A, C = oracle.tolerance_scales(x, y, z, d, kappa, gamma, u)
+    p = np.stack([x, y, z], axis=1)
+    r = d / 2
+    l = np.sqrt(((p[:, None, :] - p[None, :, :]) ** 2).sum(-1))
+    rs = r[:, None] + r[None, :]
+    delta = rs - l
+    rho = r[:, None] * r[None, :] / rs
+    eta = 4 * u * (rs + l)
+    off = ~np.eye(pop.n, dtype=bool)
+    contact = (delta > 0) & (l > 0) & off
+    band = (delta > -eta) & off
+    Sn = np.where(contact, kappa * delta + gamma * np.sqrt(rho * np.maximum(delta, 0)), 0).sum(1)
+    An = np.where(band, (kappa + gamma * np.sqrt(rho) / (2 * np.sqrt(np.maximum(delta, eta)))) * eta,
+                  0).sum(1)
+    assert C.sum() > 2000 and np.any(band & ~contact) == (u == 1e-3)
+    assert np.array_equal(C, contact.sum(1))
+    np.testing.assert_allclose(S, Sn, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(A, An, rtol=1e-12, atol=0)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The per-agent loops run on several threads; every agent's sums stay
+    sequential, so one and several threads give the same bits."""
+    pop = workloads.clusters(4000, n_clusters=3, side=300.0, seed=33)
+    arrs = pop.arrays()
+    prm = dict(P, dt=0.05, max_disp=0.02)
+    g = np.random.default_rng(3).normal(size=(pop.n, 3))
+    before = oracle.set_threads(0)
+
+    def run():
+        return (oracle.step(*arrs, prm), oracle.tolerance_scales(*arrs, 2.0, 1.0, U24),
+                oracle.neighbors(*arrs), oracle.step_adjoint(*arrs, prm, g),
+                oracle.adjoint_scales(*arrs, prm, g, U24))
+
+    try:
+        oracle.set_threads(1)
+        one = run()
+        assert oracle.set_threads(4) == 4
+        many = run()
+    finally:
+        oracle.set_threads(before)
+
+    def flat(t):
+        if isinstance(t, (tuple, list)):
+            for v in t:
+                yield from flat(v)
+        else:
+            yield np.asarray(t)
+
+    for a, b in zip(flat(one), flat(many)):
+        assert np.array_equal(a, b)
