@@ -49,8 +49,13 @@
  *   later kernels of the same workspace then do nothing and the outputs are
  *   unspecified.  ms_device_status() synchronises the stream and reports it.
  *   n = 0 is valid and does nothing.
- * Limits.  Agents and boxes are indexed with int32: n < 2^31 and the total
- *   number of boxes < 2^31.
+ * Limits.  Agents are indexed with int32 and the box-sorted payload with
+ *   32-bit byte offsets: n < 2^31 and n * (16 bytes for MS_F32 and
+ *   MS_F32_POS64, 32 for MS_F64) < 2^32.  A build holds at most 2^25 =
+ *   33,554,432 boxes over all its simulations (its two-level counting sort
+ *   keeps at most 8192 buckets of 4096 boxes): ms_workspace_init rejects a
+ *   larger max_boxes with MS_ECAPACITY, and a build whose grid needs more
+ *   boxes than max_boxes sets the capacity error.
  */
 #ifndef MECHSTEP_H
 #define MECHSTEP_H
@@ -125,7 +130,8 @@ typedef struct {
                             package's autotuner picks the faster one. */
 } ms_workspace;
 
-/* Bytes of device memory a workspace with these capacities needs. */
+/* Bytes of device memory a workspace with these capacities needs (0 for
+ * capacities out of range, including max_boxes > 2^25). */
 size_t ms_workspace_bytes(int64_t max_agents, int64_t max_boxes, int32_t max_sims,
                           ms_dtype dtype);
 
@@ -201,11 +207,35 @@ ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params
                                          void* y, void* z, void* dx, void* dy, void* dz,
                                          void* stream);
 
+/* One backward step of a rollout p_{t+1} = p_t + Delta(p_t) on the build of
+ * p_t (the derivative of ms_mech_step_integrate), all of it on the device:
+ *   pbx, pby, pbz [n]  in: dL/dp_{t+1}; out: dL/dp_t = dL/dp_{t+1} +
+ *                      (dDelta/dp_t)^T dL/dp_{t+1}, updated in place
+ *   dbar [n]           dL/dd of this step added in place
+ *   g_params           device double[2], {dL/dkappa, dL/dgamma} of this step
+ *                      added in place
+ * All three accumulators have the positions' type (float for MS_F32, double
+ * for MS_F64 and MS_F32_POS64); each step's terms are computed as in
+ * ms_mech_step_backward (FP32 arithmetic in the FP32 modes, the incoming
+ * gradient rounded to float there), converted, then added.  Walking the
+ * steps of a rollout backwards with this call gives the gradient of a loss
+ * on the final positions with respect to the initial positions, the
+ * diameters, kappa and gamma. */
+ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_params* p, void* pbx,
+                                           void* pby, void* pbz, void* dbar, double* g_params,
+                                           void* stream);
+
 /* ms_mech_step_backward per simulation; g_params: device double [2B]. */
 ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
                                         const void* gdx, const void* gdy, const void* gdz,
                                         void* gx, void* gy, void* gz, void* gd,
                                         double* g_params, void* stream);
+
+/* ms_mech_step_backward_accumulate per simulation of the last batched build;
+ * params: device ms_params [B]; g_params: device double [2B] added to. */
+ms_status ms_mech_step_backward_batched_accumulate(const ms_workspace* ws, const ms_params* params,
+                                                   void* pbx, void* pby, void* pbz, void* dbar,
+                                                   double* g_params, void* stream);
 
 /* p <- p + Delta for n agents (all agents move at once from the displacements
  * of one step).  dtype: MS_F32 (float p, float Delta), MS_F64 (double,

@@ -24,6 +24,7 @@ from ._lib import MechStepError, MS_F32, MS_F64, MS_F32_POS64  # noqa: F401
 __all__ = [
     "Workspace", "BatchSpec", "grid_build", "mech_step", "mech_step_backward",
     "grid_build_batched", "mech_step_batched", "mech_step_backward_batched", "integrate",
+    "mech_step_backward_accumulate", "mech_step_backward_batched_accumulate", "MAX_BOXES",
     "mech_step_integrate", "mech_step_batched_integrate",
     "reorder", "grid_info", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
     "params_tensor",
@@ -35,6 +36,7 @@ _DTYPES = {
     "f32_pos64": (MS_F32_POS64, torch.float64, torch.float32),
 }
 PARAM_KEYS = ("kappa", "gamma", "dt", "max_disp", "adherence")
+MAX_BOXES = 1 << 25   # boxes a build can hold over all its simulations
 
 
 def _stream(device=None) -> ctypes.c_void_p:
@@ -60,9 +62,10 @@ def params_tensor(plist, device) -> torch.Tensor:
 class Workspace:
     """Device workspace of one grid (or one batch of grids).
 
-    max_boxes defaults to 4 boxes per agent plus 4096, enough for the uniform
-    and clustered populations of the benchmarks; a build that needs more
-    reports MS_ECAPACITY through :func:`device_status`.
+    max_boxes defaults to 4 boxes per agent plus 4096 (at most MAX_BOXES =
+    2^25, the most a build can hold), enough for the uniform and clustered
+    populations of the benchmarks; a build that needs more reports
+    MS_ECAPACITY through :func:`device_status`.
     """
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
@@ -74,7 +77,7 @@ class Workspace:
         self.dtype_name = dtype
         self.code, self.in_dtype, self.out_dtype = _DTYPES[dtype]
         if max_boxes is None:
-            max_boxes = 4 * max(int(max_agents), 1) + 4096
+            max_boxes = min(4 * max(int(max_agents), 1) + 4096, MAX_BOXES)
         self.device = torch.device(device if device is not None else "cuda")
         nbytes = self.lib.ms_workspace_bytes(int(max_agents), int(max_boxes), int(max_sims), self.code)
         if nbytes == 0:
@@ -200,6 +203,39 @@ def mech_step_backward(ws: Workspace, params, gdx, gdy, gdz, out=None, g_params=
                                             _ptr(gdz), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gd),
                                             _ptr(g_params), _stream(ws.device)))
     return gx, gy, gz, gd, g_params
+
+
+def mech_step_backward_accumulate(ws: Workspace, params, pbar, dbar, g_params):
+    """One backward step of a rollout on the last plain build (of p_t):
+    pbar = (pbx, pby, pbz) holds dL/dp_{t+1} and becomes dL/dp_t in place;
+    dbar (dL/dd) and g_params (device float64 [2], dL/dkappa, dL/dgamma) are
+    added to.  pbar and dbar have the positions' dtype."""
+    n = ws.n_agents
+    _check_in(ws, *pbar, dbar, n=n)
+    _check_gp(g_params, 2)
+    p = _params(params)
+    _lib.check(ws.lib.ms_mech_step_backward_accumulate(ctypes.byref(ws.c), ctypes.byref(p),
+                                                       *(_ptr(a) for a in pbar), _ptr(dbar),
+                                                       _ptr(g_params), _stream(ws.device)))
+
+
+def mech_step_backward_batched_accumulate(ws: Workspace, params_dev, pbar, dbar, g_params):
+    """mech_step_backward_accumulate for every simulation of the last batched
+    build; g_params: device float64 [B, 2] (or [2B]) added to."""
+    n = ws.n_agents
+    _check_in(ws, *pbar, dbar, n=n)
+    if params_dev.shape != (ws.n_sims, 5) or params_dev.dtype != torch.float64:
+        raise ValueError(f"params must be float64 [{ws.n_sims}, 5]")
+    _check_gp(g_params, 2 * ws.n_sims)
+    _lib.check(ws.lib.ms_mech_step_backward_batched_accumulate(
+        ctypes.byref(ws.c), _ptr(params_dev), *(_ptr(a) for a in pbar), _ptr(dbar), _ptr(g_params),
+        _stream(ws.device)))
+
+
+def _check_gp(g, numel):
+    if (not isinstance(g, torch.Tensor) or g.device.type != "cuda" or g.dtype != torch.float64
+            or not g.is_contiguous() or g.numel() != numel):
+        raise ValueError(f"g_params must be a contiguous float64 device tensor of {numel} elements")
 
 
 def grid_build_batched(ws: Workspace, x, y, z, d, spec: BatchSpec):

@@ -4,10 +4,12 @@
   backward through ``ms_mech_step_backward``.
 * :func:`rollout`    T steps p_{t+1} = p_t + Delta(p_t) with the grid rebuilt
   every step (Section IV-A).  Only every K-th position is stored; backward
-  recomputes each K-step segment from its checkpoint and walks it in reverse,
-  pbar_t = pbar_{t+1} + J_Delta(p_t)^T pbar_{t+1}, accumulating the gradients
-  of the diameters and of kappa, gamma.  Every kernel sums in a fixed order,
-  so the recomputed trajectory and the gradients do not depend on K.
+  recomputes each K-step segment from its checkpoint and walks it in reverse
+  with ``ms_mech_step_backward_accumulate``, which forms
+  pbar_t = pbar_{t+1} + J_Delta(p_t)^T pbar_{t+1} and adds the gradients of
+  the diameters and of kappa, gamma on the device (this module only
+  allocates, copies and calls).  Every kernel sums in a fixed order, so the
+  recomputed trajectory and the gradients do not depend on K.
 
 kappa and gamma may be Python floats or 0-d CPU float64 tensors (the
 parameters are passed to the kernels by value, so a device tensor would force
@@ -17,7 +19,8 @@ from __future__ import annotations
 
 import torch
 
-from . import grid_build, integrate, mech_step, mech_step_backward, Workspace
+from . import (grid_build, integrate, mech_step, mech_step_backward,
+               mech_step_backward_accumulate, Workspace)
 
 
 def _f(v) -> float:
@@ -94,7 +97,7 @@ class _Rollout(torch.autograd.Function):
         ref = ctx.ckpts[0][0]
         pbar = [(g if g is not None else torch.zeros_like(ref)).to(ref.dtype).contiguous().clone()
                 for g in (gx, gy, gz)]
-        dbar = torch.zeros(d.numel(), dtype=ws.out_dtype, device=d.device)
+        dbar = torch.zeros(d.numel(), dtype=ref.dtype, device=d.device)
         kg = torch.zeros(2, dtype=torch.float64, device=d.device)
         for s0 in sorted(ctx.ckpts, reverse=True):
             s1 = min(s0 + K, steps)
@@ -108,13 +111,7 @@ class _Rollout(torch.autograd.Function):
                     integrate(*pos, *D)
             for t in range(s1 - 1, s0 - 1, -1):
                 grid_build(ws, *traj[t - s0], d, edge)
-                g = [a.to(ws.out_dtype).contiguous() for a in pbar]
-                ox, oy, oz, od, gkg = mech_step_backward(ws, p, *g)
-                pbar[0] += ox.to(ref.dtype)
-                pbar[1] += oy.to(ref.dtype)
-                pbar[2] += oz.to(ref.dtype)
-                dbar += od
-                kg += gkg
+                mech_step_backward_accumulate(ws, p, pbar, dbar, kg)
         kappa, gamma = ctx.kg_ref
         return (pbar[0], pbar[1], pbar[2], dbar.to(d.dtype), _grad_like(kg[0], kappa),
                 _grad_like(kg[1], gamma), None, None, None, None, None)

@@ -23,6 +23,12 @@
 //                 (block, simulation) pair at index block + simulation.
 //   k_reduce_params  one block per simulation sums its partials in a fixed
 //                 order, so repeated runs give identical bits.
+//
+// Rollout mode (ACC): the incoming gradient is dL/dp_{t+1} in the position
+// arrays themselves (the state's precision), and the pass turns it into
+// dL/dp_t = dL/dp_{t+1} + J^T dL/dp_{t+1} in place, adds the diameter
+// gradient to a running sum and the kappa/gamma gradients to running sums:
+// one backward step of a rollout p_{t+1} = p_t + Delta(p_t).
 #include "gather.hpp"
 #include "launch.hpp"
 
@@ -98,16 +104,16 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
 // k_bwd_fbar gathers one record per agent instead of three values; and the
 // outgoing gradient records split into the caller's arrays.  Both passes are
 // coalesced.
-template <typename Pay, typename Real>
-__global__ __launch_bounds__(kBlock) void k_pack3(const Real* __restrict__ a, const Real* __restrict__ b,
-                                                  const Real* __restrict__ c, int64_t n,
+template <typename Pay, typename Real, typename G>
+__global__ __launch_bounds__(kBlock) void k_pack3(const G* __restrict__ a, const G* __restrict__ b,
+                                                  const G* __restrict__ c, int64_t n,
                                                   const Header* __restrict__ hdr, Pay* __restrict__ out)
 {
     if (hdr->error) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     Pay v;
-    v.x = a[i]; v.y = b[i]; v.z = c[i]; v.w = (Real)0;
+    v.x = (Real)a[i]; v.y = (Real)b[i]; v.z = (Real)c[i]; v.w = (Real)0;
     out[i] = v;
 }
 
@@ -122,6 +128,21 @@ __global__ __launch_bounds__(kBlock) void k_split4(const Pay* __restrict__ in, i
     if (i >= n) return;
     const Pay v = in[i];
     a[i] = v.x; b[i] = v.y; c[i] = v.z; d[i] = v.w;
+}
+
+// Rollout mode: pbar += J^T pbar and dbar += (gradient of the diameters),
+// in the state's precision In (each term converted first, then added).
+template <typename Pay, typename In>
+__global__ __launch_bounds__(kBlock) void k_split4_acc(const Pay* __restrict__ in, int64_t n,
+                                                       const Header* __restrict__ hdr,
+                                                       In* __restrict__ a, In* __restrict__ b,
+                                                       In* __restrict__ c, In* __restrict__ d)
+{
+    if (hdr->error) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Pay v = in[i];
+    a[i] += (In)v.x; b[i] += (In)v.y; c[i] += (In)v.z; d[i] += (In)v.w;
 }
 
 // Deterministic block sum: butterfly inside each wave, waves in fixed order.
@@ -250,7 +271,7 @@ constexpr int kReduceThreads = 1024;   // threads of the one block per simulatio
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_params(const double* __restrict__ partials,
                                                           const int64_t* __restrict__ off,
                                                           int64_t n, const Header* __restrict__ hdr,
-                                                          double* __restrict__ out)
+                                                          double* __restrict__ out, bool acc)
 {
     __shared__ double s_w[kReduceThreads / kWave];
     if (hdr->error) return;
@@ -269,35 +290,40 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_params(const double* 
     tk = block_sum_fixed<kReduceThreads>(tk, s_w);
     tg = block_sum_fixed<kReduceThreads>(tg, s_w);
     if (threadIdx.x == 0) {
-        out[2 * s] = tk;
-        out[2 * s + 1] = tg;
+        out[2 * s] = acc ? out[2 * s] + tk : tk;
+        out[2 * s + 1] = acc ? out[2 * s + 1] + tg : tg;
     }
 }
 
+// acc: rollout mode (gdx..gdz are gx..gz, arrays of the state type In).
 template <int M, int LIST>
 hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                         const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
-                        double* g_params, hipStream_t s)
+                        double* g_params, bool acc, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
+    using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     const Pay* pay = static_cast<const Pay*>(D.payload);
     Pay* fb = static_cast<Pay*>(D.fbar);
-    const Real *GX = (const Real*)gdx, *GY = (const Real*)gdy, *GZ = (const Real*)gdz;
-    Real *OX = (Real*)gx, *OY = (Real*)gy, *OZ = (Real*)gz, *OD = (Real*)gd;
     ms_params dummy{};
     // pay2 (free after the build) holds the packed incoming gradient, then the
     // packed outgoing one
     Pay* rec = static_cast<Pay*>(D.pay2);
-    k_pack3<Pay, Real><<<nb, kBlock, 0, s>>>(GX, GY, GZ, n, D.hdr, rec);
+    if (acc)
+        k_pack3<Pay, Real, In><<<nb, kBlock, 0, s>>>((const In*)gdx, (const In*)gdy, (const In*)gdz,
+                                                     n, D.hdr, rec);
+    else
+        k_pack3<Pay, Real, Real><<<nb, kBlock, 0, s>>>((const Real*)gdx, (const Real*)gdy,
+                                                       (const Real*)gdz, n, D.hdr, rec);
     if (batched) {
         k_bwd_fbar<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
                                                    dummy, p_dev, D.hdr, rec, fb, nullptr, D.pay32);
         k_bwd_gather<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
                                                      n, dummy, p_dev, D.hdr, rec, D.partials, D.pay32);
-        k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params);
+        k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params, acc);
     } else {
         k_bwd_fbar<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
@@ -305,9 +331,13 @@ hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
         k_bwd_gather<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
                                                       D.partials, D.pay32);
-        k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params);
+        k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params, acc);
     }
-    k_split4<Pay, Real><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, OX, OY, OZ, OD);
+    if (acc)
+        k_split4_acc<Pay, In><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, (In*)gx, (In*)gy, (In*)gz, (In*)gd);
+    else
+        k_split4<Pay, Real><<<nb, kBlock, 0, s>>>(rec, n, D.hdr, (Real*)gx, (Real*)gy, (Real*)gz,
+                                                  (Real*)gd);
     return hipGetLastError();
 }
 
@@ -317,13 +347,13 @@ template <int M>
 hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                          const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                          const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
-                         double* g_params, int list, hipStream_t s)
+                         double* g_params, int list, bool acc, hipStream_t s)
 {
     if (list == kLongList)
         return backward_run<M, kLongList>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
-                                          gz, gd, g_params, s);
+                                          gz, gd, g_params, acc, s);
     return backward_run<M, kMaxContacts>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
-                                         gz, gd, g_params, s);
+                                         gz, gd, g_params, acc, s);
 }
 
 }  // namespace
@@ -331,18 +361,18 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, int list, hipStream_t s)
+                           void* gd, double* g_params, int list, bool acc, hipStream_t s)
 {
     switch (L.dtype) {
     case MS_F32:
         return backward_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, list, s);
+                                     gd, g_params, list, acc, s);
     case MS_F64:
         return backward_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, list, s);
+                                     gd, g_params, list, acc, s);
     case MS_F32_POS64:
         return backward_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx,
-                                           gy, gz, gd, g_params, list, s);
+                                           gy, gz, gd, g_params, list, acc, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -79,7 +79,7 @@ extern "C" {
 
 size_t ms_workspace_bytes(int64_t max_agents, int64_t max_boxes, int32_t max_sims, ms_dtype dtype)
 {
-    if (max_agents < 0 || max_boxes < 0 || max_sims < 1) return 0;
+    if (max_agents < 0 || max_boxes < 0 || max_boxes > ms::kMaxBoxes || max_sims < 1) return 0;
     return ms::make_layout(max_agents, max_boxes, max_sims, dtype).total;
 }
 
@@ -93,8 +93,9 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
         return fail(MS_EINVAL, "ms_workspace_init: unknown dtype %d", (int)dtype);
     if (max_agents < 0 || max_agents >= 2147483647LL)
         return fail(MS_ECAPACITY, "ms_workspace_init: max_agents must be in [0, 2^31-1)");
-    if (max_boxes < 1 || max_boxes >= 2147483647LL)
-        return fail(MS_ECAPACITY, "ms_workspace_init: max_boxes must be in [1, 2^31-1)");
+    if (max_boxes < 1 || max_boxes > ms::kMaxBoxes)
+        return fail(MS_ECAPACITY, "ms_workspace_init: max_boxes must be in [1, 2^25] (a build sorts "
+                                  "at most 8192 buckets of 4096 boxes)");
     if (max_sims < 1 || max_sims > (1 << 24))
         return fail(MS_ECAPACITY, "ms_workspace_init: max_sims must be in [1, 2^24]");
     const uint64_t pay_bytes = (uint64_t)max_agents * (dtype == MS_F64 ? 32u : 16u);
@@ -264,10 +265,12 @@ ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params
                      who);
 }
 
+// acc: rollout mode (gdx..gdz are gx..gz, the position gradients in the
+// positions' type, updated in place; gd and g_params are added to).
 static ms_status backward_common(const ms_workspace* ws, bool batched, const ms_params* p,
                                  const void* gdx, const void* gdy, const void* gdz, void* gx,
-                                 void* gy, void* gz, void* gd, double* g_params, void* stream,
-                                 const char* who)
+                                 void* gy, void* gz, void* gd, double* g_params, bool acc,
+                                 void* stream, const char* who)
 {
     ms_status st = step_common(ws, batched ? 2 : 1, who);
     if (st) return st;
@@ -280,10 +283,12 @@ static ms_status backward_common(const ms_workspace* ws, bool batched, const ms_
     const int64_t n = ws->n_agents;
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     if (n == 0) return ok();
-    if ((st = check_arrays(who, out_size(ws->dtype), {gdx, gdy, gdz, gx, gy, gz, gd}))) return st;
+    if ((st = check_arrays(who, acc ? in_size(ws->dtype) : out_size(ws->dtype),
+                           {gdx, gdy, gdz, gx, gy, gz, gd})))
+        return st;
     return check_hip(ms::launch_backward(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
                                          batched, batched ? nullptr : p, batched ? p : nullptr, gdx,
-                                         gdy, gdz, gx, gy, gz, gd, g_params, gather_list(ws),
+                                         gdy, gdz, gx, gy, gz, gd, g_params, gather_list(ws), acc,
                                          as_stream(stream)),
                      who);
 }
@@ -292,8 +297,16 @@ ms_status ms_mech_step_backward(const ms_workspace* ws, const ms_params* p, cons
                                 const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
                                 void* gd, double* g_params, void* stream)
 {
-    return backward_common(ws, false, p, gdx, gdy, gdz, gx, gy, gz, gd, g_params, stream,
+    return backward_common(ws, false, p, gdx, gdy, gdz, gx, gy, gz, gd, g_params, false, stream,
                            "ms_mech_step_backward");
+}
+
+ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_params* p,
+                                           void* pbx, void* pby, void* pbz, void* dbar,
+                                           double* g_params, void* stream)
+{
+    return backward_common(ws, false, p, pbx, pby, pbz, pbx, pby, pbz, dbar, g_params, true, stream,
+                           "ms_mech_step_backward_accumulate");
 }
 
 ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
@@ -301,8 +314,16 @@ ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params*
                                         void* gy, void* gz, void* gd, double* g_params,
                                         void* stream)
 {
-    return backward_common(ws, true, params, gdx, gdy, gdz, gx, gy, gz, gd, g_params, stream,
+    return backward_common(ws, true, params, gdx, gdy, gdz, gx, gy, gz, gd, g_params, false, stream,
                            "ms_mech_step_backward_batched");
+}
+
+ms_status ms_mech_step_backward_batched_accumulate(const ms_workspace* ws, const ms_params* params,
+                                                   void* pbx, void* pby, void* pbz, void* dbar,
+                                                   double* g_params, void* stream)
+{
+    return backward_common(ws, true, params, pbx, pby, pbz, pbx, pby, pbz, dbar, g_params, true,
+                           stream, "ms_mech_step_backward_batched_accumulate");
 }
 
 ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy, const void* dz,
@@ -446,7 +467,9 @@ ms_status ms_device_status(const ms_workspace* ws, void* stream)
     if ((st = check_hip(e, who))) return st;
     if (err & (ms::ERR_NONFINITE | ms::ERR_NEGDIAM))
         return fail(MS_EINPUT, "non-finite position/diameter or negative diameter (bits %u)", err);
-    if (err & ms::ERR_CAPACITY) return fail(MS_ECAPACITY, "more boxes than the workspace holds (bits %u)", err);
+    if (err & ms::ERR_CAPACITY)
+        return fail(MS_ECAPACITY, "the grid needs more boxes than the workspace holds (max_boxes, "
+                                  "at most 2^25) (bits %u)", err);
     if (err) return fail(MS_EINVAL, "edge or simulation offsets invalid (bits %u)", err);
     return ok();
 }

@@ -23,13 +23,19 @@ constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
+// Boxes a build can hold over all its simulations: the two-level sort keeps at
+// most kBucketsMax buckets of at most 2^kSBMax boxes.
+constexpr int64_t kMaxBoxes = (int64_t)kBucketsMax << kSBMax;
+// The gather addresses each box's (start, split word) pair with a 32-bit byte
+// offset of 8 bytes per box (two extra boxes past the last one).
+static_assert((kMaxBoxes + 2) * 8 < (int64_t(1) << 32), "32-bit box-word offsets of the gather");
 
 // Device error bits (ms_grid_info.error and the workspace error word).
 enum : uint32_t {
     ERR_NONFINITE = 1u,   // non-finite position or diameter
     ERR_NEGDIAM = 2u,     // negative diameter
     ERR_EDGE = 4u,        // edge <= 0, non-finite, or below the largest diameter
-    ERR_CAPACITY = 8u,    // more boxes than the workspace holds (or int32 overflow)
+    ERR_CAPACITY = 8u,    // more boxes than the workspace holds (at most kMaxBoxes)
     ERR_OFFSETS = 16u,    // simulation offsets do not partition [0, n)
 };
 

@@ -28,10 +28,12 @@ hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
                         hipStream_t s);
 
 // Backward step; list: contact-list length of its gathers (as launch_force).
+// acc: rollout mode, gdx..gdz == gx..gz are the position gradients of the
+// state type, updated in place (pbar += J^T pbar); gd and g_params are added to.
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, int list, hipStream_t s);
+                           void* gd, double* g_params, int list, bool acc, hipStream_t s);
 
 hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                             const void* dz, int64_t n, int dtype, hipStream_t s);

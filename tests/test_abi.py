@@ -71,6 +71,21 @@ def test_host_validation_errors(lib):
     assert lib.ms_copy_probe(ctypes.c_void_p(16), ctypes.c_void_p(32), 17, None) == _lib.MS_EINVAL
 
 
+def test_box_capacity_limit(lib):
+    """A build holds at most 2^25 boxes (8192 buckets of 4096 boxes in the
+    two-level sort); larger capacities are refused before any device work."""
+    from paper_2105_00039_amd import _lib, MAX_BOXES
+    assert MAX_BOXES == 1 << 25
+    assert lib.ms_workspace_bytes(1000, 1 << 25, 1, _lib.MS_F32) > 0
+    assert lib.ms_workspace_bytes(1000, (1 << 25) + 1, 1, _lib.MS_F32) == 0
+    ws = _lib.ms_workspace()
+    for boxes in ((1 << 25) + 1, 1 << 29, (1 << 31) - 2):
+        st = lib.ms_workspace_init(ctypes.byref(ws), ctypes.c_void_p(256), 1 << 45, 1000, boxes, 1,
+                                   _lib.MS_F32, None)
+        assert st == _lib.MS_ECAPACITY, boxes
+        assert b"2^25" in lib.ms_last_error()
+
+
 def test_struct_layouts_match_header(tmp_path):
     """ctypes mirrors of the header structs have the C compiler's sizes and offsets."""
     import subprocess
