@@ -1,27 +1,31 @@
 """Benchmark of the mechanical-interaction step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
-                    [--neighbors 12] [--no-cpu] [--no-extras]
+                    [--neighbors 12] [--order sorted|caller] [--no-cpu] [--no-extras]
 
 A step is one pass of the whole hot path over the population: uniform-grid
 build (bounds, binning, counts, scan, stable scatter), 27-box gather with the
 Eq. 1 force and the displacement rule, and the position update.  The headline
 workload is 2,097,152 agents uniform in a cube sized for ~12 neighbours within
-the interaction radius 12, diameters U[8, 12], FP32.  Inputs are resident in
-device memory before timing starts.  The timed region replays a HIP graph of
-one step K times.
+the interaction radius 12, diameters U[8, 12], FP32, stepped as a rollout
+whose state is kept in the box-sorted slot order of each build (the agent
+sorting of the paper's Section IV-D: ms_mech_step_integrate_sorted writes the
+state after the step renumbered into the other of two buffers, so every
+store is coalesced).  Inputs are resident in device memory before timing
+starts.  The timed region replays HIP graphs of one step, K times.
 
 One JSON line is printed with, besides the headline value:
-  roofline      the force step's algorithmic flops per call (9 per 27-box
+  roofline      the force kernel's algorithmic flops per launch (9 per 27-box
                 candidate + 25 per contact, the measured candidate and contact
                 counts of the workload) over its mean duration from HIP events
-                around every ms_mech_step call of an eager K-step pass (the
-                gather kernel k_force and the record split k_soa), against the
-                FP32 vector peak; traffic (HBM bytes of both kernels from
-                rocprofv3 counters) is filled from the committed profile summary
-                when it was taken on the current sources.
-  cpu_baseline  the FP64 oracle (single thread) on the same population.
-  variants      other densities / FP64, fwd+bwd and the batched workload.
+                around every force launch of an eager K-step pass, against the
+                FP32 vector peak; traffic (HBM bytes from rocprofv3 counters)
+                and the issue counters are filled from the committed profile
+                summaries when they were taken on the current sources.
+  cpu_baseline  the FP64 oracle (-O3 -march=native) on the same population,
+                on all of this process's host cores and on one.
+  variants      other densities / FP64 / the caller-order state / clusters,
+                fwd+bwd, the differentiated rollout and the batched workload.
 """
 from __future__ import annotations
 
@@ -52,8 +56,12 @@ def bytes_alg(n, n_boxes, S):
     return (22 * S + 16) * n + 20 * n_boxes
 
 
-def force_bytes(n, n_boxes, S):
-    """Force kernel: payload 4S + perm 4 read, 3S written per agent; start 4 per box."""
+def force_bytes(n, n_boxes, S, sorted_state=False):
+    """Force step, per agent: payload 4S read and displacements 3S written,
+    plus perm 4 read (caller order) or the state after the step 4S written
+    (sorted state); box starts 4 per box."""
+    if sorted_state:
+        return 11 * S * n + 4 * n_boxes
     return (7 * S + 4) * n + 4 * n_boxes
 
 
@@ -89,15 +97,25 @@ def contacts_per_agent(x, y, z, d, counts, lst):
     return K / counts.numel()
 
 
-def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, backward=False):
-    """Returns (seconds for `steps` steps, mean force-kernel ms or None)."""
+def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, backward=False,
+               sorted_state=False):
+    """Returns (seconds for `steps` steps, mean force-step ms or None, ws, state).
+
+    A step is grid build + force + displacement + integrate.  sorted_state:
+    the rollout keeps its state in the build's slot order
+    (ms_mech_step_integrate_sorted writes the state after the step into the
+    other of two buffers, positions and diameters renumbered together);
+    otherwise the state stays in the caller's order (ms_mech_step_integrate
+    adds the displacements in place).  Both write the displacements too."""
     n = arrs[0].size
     # The differentiated step keeps the forward's forces for the backward of
     # the same build and parameters, as the autograd rollout does.
     ws = ms.Workspace(n, dtype=dtype, keep_forces=backward)
     in_t = torch.float32 if dtype == "f32" else torch.float64
     t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in arrs]
-    x0 = [a.clone() for a in t[:3]]
+    x0 = [a.clone() for a in t]
+    bufs = [t, [torch.empty_like(a) for a in t]] if sorted_state else [t]
+    cur = [0]
     out = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
     gout = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(4))
     gkg = torch.empty(2, dtype=torch.float64, device="cuda")
@@ -107,20 +125,29 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     ms.grid_build(ws, *t)
     ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
 
-    def one(ev=None):
-        ms.grid_build(ws, *t)
+    def one(ev=None, c=None):
+        """One step from state buffer c (default: the current one)."""
+        c = cur[0] if c is None else c
+        src = bufs[c]
+        ms.grid_build(ws, *src)
         if ev is not None:
-            # roofline pass: events around the displacement step alone
             ev[0].record()
+        if sorted_state:
+            ms.mech_step_integrate_sorted(ws, PARAMS, *src, state_out=bufs[1 - c], disp_out=out)
+        elif ev is not None:
+            # roofline pass: events around the displacement step alone
             ms.mech_step(ws, PARAMS, out=out)
-            ev[1].record()
         else:
             # rollout step: displacements written and added to the positions
-            ms.mech_step_integrate(ws, PARAMS, *t[:3], out=out)
+            ms.mech_step_integrate(ws, PARAMS, *src[:3], out=out)
+        if ev is not None:
+            ev[1].record()
         if backward:
             ms.mech_step_backward(ws, PARAMS, *gin, out=gout, g_params=gkg)
-        if ev is not None:
-            ms.integrate(*t[:3], *out)
+        if ev is not None and not sorted_state:
+            ms.integrate(*src[:3], *out)
+        if sorted_state:
+            cur[0] = 1 - c
 
     for _ in range(warmup):
         one()
@@ -147,17 +174,29 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
             one()
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
-        gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr):
-            one()
+        # one graph per state buffer (a sorted rollout alternates between two)
+        graphs = []
+        saved = cur[0]
+        for c in range(len(bufs)):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                one(c=c)
+            graphs.append(gr)
+        cur[0] = saved                   # capturing executes nothing
+
+        def replay():
+            graphs[cur[0]].replay()
+            if sorted_state:
+                cur[0] = 1 - cur[0]
+
         for _ in range(max(warmup, 1)):
-            gr.replay()
+            replay()
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(steps):
-            gr.replay()
+            replay()
         b.record()
         torch.cuda.synchronize()
         total = a.elapsed_time(b) / 1e3
@@ -172,58 +211,51 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
         torch.cuda.synchronize()
         total = a.elapsed_time(b) / 1e3
     ms.device_status(ws)
-    for a_, b_ in zip(t[:3], x0):
+    for a_, b_ in zip(t, x0):
         a_.copy_(b_)
     return total, force_ms, ws, t
 
 
-def time_sorted_state(ms, torch, arrs, dtype, steps, warmup, reps=10):
-    """Steps on the same population renumbered into the slot order of its
-    first build (box-sorted state, as a rollout that reorders its state
-    keeps it), and the time to reorder the four state arrays once: from the
-    random input order (first_reorder_us) and from the sorted state after one
-    step of motion (reorder_us, what a rollout pays per reorder)."""
-    n = arrs[0].size
+def time_rollout_grad(ms, torch, dtype, steps=50, ckpt=10, reps=2, seed=0):
+    """The differentiation workload: 262,144 agents at ~12 neighbours, a
+    `steps`-step rollout with checkpoints every `ckpt` steps, loss = mean
+    squared distance of the final positions to seeded targets, gradients with
+    respect to the initial positions, diameters, kappa and gamma.  Timed with
+    events around the forward rollout plus its backward (segment recompute
+    from the checkpoints and the accumulating backward steps)."""
+    from paper_2105_00039_amd import autograd as msa, workloads
+    pop = workloads.workload("adjoint262k", seed=seed)
+    tgt = workloads.targets(pop, seed=seed)
     in_t = torch.float32 if dtype == "f32" else torch.float64
-    ws = ms.Workspace(n, dtype=dtype)
-    t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in arrs]
-    out = [torch.empty_like(a) for a in t]
+    rest = dict(dt=PARAMS["dt"], max_disp=PARAMS["max_disp"], adherence=PARAMS["adherence"])
+    ws = ms.Workspace(pop.n, dtype=dtype)
+    base = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda", in_t) for a in pop.arrays()]
+    tx, ty, tz = (torch.from_numpy(np.asarray(a)).to("cuda", in_t) for a in tgt)
 
-    def reorder_us():
-        for a, o in zip(t, out):
-            ms.reorder(ws, a, out=o)
-        a0 = torch.cuda.Event(enable_timing=True)
-        a1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a0.record()
-        for _ in range(reps):
-            for a, o in zip(t, out):
-                ms.reorder(ws, a, out=o)
-        a1.record()
-        torch.cuda.synchronize()
-        ms.device_status(ws)
-        return a0.elapsed_time(a1) / reps * 1e3
+    def once():
+        t = [a.clone().requires_grad_(True) for a in base]
+        k = torch.tensor(PARAMS["kappa"], dtype=torch.float64, requires_grad=True)
+        g = torch.tensor(PARAMS["gamma"], dtype=torch.float64, requires_grad=True)
+        px, py, pz = msa.rollout(*t, k, g, ws, rest, steps, ckpt)
+        L = ((px - tx) ** 2 + (py - ty) ** 2 + (pz - tz) ** 2).mean()
+        L.backward()
+        return L
 
-    ms.grid_build(ws, *t)
-    first_us = reorder_us()
-    sarrs = [o.cpu().numpy() for o in out]
-    # one step of motion on the sorted state, then the reorder a rollout does
-    for a, o in zip(t, out):
-        a.copy_(o)
-    disp = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
-    ms.grid_build(ws, *t)
-    ms.mech_step(ws, PARAMS, out=disp)
-    ms.integrate(*t[:3], *disp)
-    ms.grid_build(ws, *t)
-    steady_us = reorder_us()
-    del ws, t, out, disp
-    sec, _, _, _ = time_plain(ms, torch, sarrs, dtype, steps, warmup, graph=True)
-    return dict(value=n * steps / sec, unit="agent-steps/s", ms_per_step=sec / steps * 1e3,
-                reorder_us=steady_us, first_reorder_us=first_us,
-                what="graph-replayed steps on the box-sorted state (ms_reorder of x, y, z, d "
-                     "into the slot order of the first build); reorder_us: one reorder of the "
-                     "four arrays of a sorted state after a step of motion; first_reorder_us: "
-                     "the same from the random input order")
+    once()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        once()
+    b.record()
+    torch.cuda.synchronize()
+    ms.device_status(ws)
+    sec = a.elapsed_time(b) / 1e3 / reps
+    return dict(value=pop.n * steps / sec, unit="agent-steps/s", ms_per_rollout=sec * 1e3,
+                n_agents=pop.n, steps=steps, ckpt_every=ckpt, dtype=dtype,
+                what="forward rollout + backward (recompute from checkpoints, accumulating "
+                     "backward steps) per agent-step of the rollout; eager, events around both")
 
 
 def time_host_state(ms, torch, arrs, steps, warmup):
@@ -325,12 +357,17 @@ def time_growing(ms, torch, steps, seed=0, n0=1_048_576, growth=1.04):
                      "per step on one workspace, events around each step")
 
 
-def time_batched(ms, torch, steps, warmup, seed=0):
+def time_batched(ms, torch, steps, warmup, seed=0, sorted_state=True):
+    """The batched workload: 256 simulations in one build and one force
+    launch per step, FP32 force with FP64 positions; graph-replayed steps
+    (sorted_state: the state kept in the build's slot order, two buffers)."""
     from paper_2105_00039_amd import workloads
     b = workloads.batched(seed=seed)
     n = b.n
     ws = ms.Workspace(n, max_sims=b.n_sims, dtype="f32_pos64")
     t = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in b.arrays(np.float64)]
+    bufs = [t, [torch.empty_like(a) for a in t]] if sorted_state else [t]
+    cur = [0]
     spec = ms.BatchSpec(b.offsets)
     P = ms.params_tensor([dict(PARAMS, kappa=float(k), gamma=float(g)) for k, g in zip(b.kappa, b.gamma)],
                          "cuda")
@@ -339,9 +376,14 @@ def time_batched(ms, torch, steps, warmup, seed=0):
     ms.grid_build_batched(ws, *t, spec)
     tuning = autotune.tune(ws, lambda: ms.mech_step_batched(ws, P, out=out))
 
-    def one():
-        ms.grid_build_batched(ws, *t, spec)
-        ms.mech_step_batched_integrate(ws, P, *t[:3], out=out)
+    def one(c=None):
+        c = cur[0] if c is None else c
+        ms.grid_build_batched(ws, *bufs[c], spec)
+        if sorted_state:
+            ms.mech_step_batched_integrate_sorted(ws, P, *bufs[c], state_out=bufs[1 - c], disp_out=out)
+            cur[0] = 1 - c
+        else:
+            ms.mech_step_batched_integrate(ws, P, *bufs[c][:3], out=out)
 
     for _ in range(warmup):
         one()
@@ -353,16 +395,27 @@ def time_batched(ms, torch, steps, warmup, seed=0):
         one()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
-    gr = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(gr):
-        one()
-    gr.replay()
+    graphs = []
+    saved = cur[0]
+    for c in range(len(bufs)):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            one(c=c)
+        graphs.append(gr)
+    cur[0] = saved
+
+    def replay():
+        graphs[cur[0]].replay()
+        if sorted_state:
+            cur[0] = 1 - cur[0]
+
+    replay()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(steps):
-        gr.replay()
+        replay()
     e.record()
     torch.cuda.synchronize()
     ms.device_status(ws)
@@ -370,24 +423,85 @@ def time_batched(ms, torch, steps, warmup, seed=0):
     return dict(value=n * steps / sec, unit="agent-steps/s", n_sims=b.n_sims, n_agents=n, steps=steps,
                 ms_per_step=sec / steps * 1e3, dtype="f32 force, f64 positions",
                 gather_list=tuning["choice"],
+                state_order="box-sorted slot order" if sorted_state else "caller order",
                 workload="batched256: sizes 10^U(3,5), 4-30 neighbours, kappa U[1,4], gamma U[0.5,2]")
 
 
-def cpu_baseline(arrs, budget_s=12.0, max_steps=3):
+def host_cpu():
+    """CPU model, sockets, cores and NUMA nodes of the host (lscpu), and the
+    CPUs this process may run on."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return dict(model=info.get("Model name", "unknown"), sockets=info.get("Socket(s)"),
+                cores_per_socket=info.get("Core(s) per socket"),
+                threads_per_core=info.get("Thread(s) per core"), numa_nodes=info.get("NUMA node(s)"),
+                allowed_cpus=len(os.sched_getaffinity(0)))
+
+
+def numa_node0_cpus():
+    """CPUs of NUMA node 0 (sysfs), or None."""
+    path = "/sys/devices/system/node/node0/cpulist"
+    if not os.path.exists(path):
+        return None
+    cpus = set()
+    for part in open(path).read().strip().split(","):
+        if "-" in part:
+            a, b = part.split("-")
+            cpus.update(range(int(a), int(b) + 1))
+        elif part:
+            cpus.add(int(part))
+    return cpus
+
+
+def cpu_baseline(arrs, budget_s=8.0, max_steps=6):
+    """The FP64 oracle timed on the host's cores, as the paper times its CPU
+    baseline (Section V): the -O3 -march=native build, one thread, then
+    OpenMP over the CPU share of this process (at most OMP_NUM_THREADS, else
+    16), kept on one NUMA node when the host has several.  Each agent's sums
+    are sequential in both, so the results are the same."""
     import oracle
+    host = host_cpu()
+    allowed = os.sched_getaffinity(0)
+    node0 = numa_node0_cpus()
+    pinned = False
+    if host.get("numa_nodes") not in (None, "1") and node0 and (allowed & node0):
+        os.sched_setaffinity(0, allowed & node0)      # before the OpenMP threads start
+        pinned = True
+    use = os.sched_getaffinity(0)
+    threads = min(len(use), int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    oracle.use_native()
     a64 = [np.asarray(a, dtype=np.float64) for a in arrs]
     n = a64[0].size
-    done = 0
-    t0 = time.perf_counter()
-    while done < max_steps:
-        oracle.step(*a64, PARAMS)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    sec = time.perf_counter() - t0
-    return dict(value=n * done / sec, unit="agent-steps/s", cores=1, kind="oracle",
-                sample=f"{done} full step(s) (grid + force + displacement) of the same {n}-agent "
-                       f"population, FP64, single thread, {sec:.1f} s")
+
+    def run(t):
+        oracle.set_threads(t)
+        done = 0
+        t0 = time.perf_counter()
+        while done < max_steps:
+            oracle.step(*a64, PARAMS)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return done, time.perf_counter() - t0
+
+    d1, s1 = run(1)
+    dn, sn = run(threads)
+    if pinned:
+        os.sched_setaffinity(0, allowed)
+    return dict(value=n * dn / sn, unit="agent-steps/s", cores=threads, kind="oracle",
+                single_thread_value=n * d1 / s1, host=dict(host, numa_pinned=pinned),
+                build="gcc -O3 -march=native -ffp-contract=off -fopenmp",
+                sample=f"full steps (grid + force + displacement) of the same {n}-agent population, "
+                       f"FP64: {dn} step(s) on {threads} threads in {sn:.1f} s, {d1} step(s) on one "
+                       f"thread in {s1:.1f} s")
 
 
 FORCE_SOURCES = ("paper_2105_00039_amd/csrc/force.hip", "paper_2105_00039_amd/csrc/gather.hpp",
@@ -465,6 +579,9 @@ def main():
                          "batched line's 256 simulations, graph-replayed steps)")
     ap.add_argument("--backward", action="store_true",
                     help="with --profile-only: eager steps with the backward step as well")
+    ap.add_argument("--order", default="sorted", choices=["sorted", "caller"],
+                    help="state order of the rollout: the build's slot order (sorted, the "
+                         "headline) or the caller's order")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="with --profile-only: also run the copy probe once on MIB MiB "
                          "(the known-size kernel that scales rocprofv3 byte counters)")
@@ -492,7 +609,7 @@ def main():
     if args.profile_only:
         if args.workload == "batched256":
             del pop, arrs
-            b = time_batched(ms, torch, args.steps, args.warmup)
+            b = time_batched(ms, torch, args.steps, args.warmup, sorted_state=args.order == "sorted")
             log(f"batched {b['n_sims']} simulations, {b['n_agents']} agents: {b['ms_per_step']:.3f} ms/step, "
                 f"{b['value']:.3e} agent-steps/s, list {b['gather_list']}")
             return
@@ -503,7 +620,7 @@ def main():
             args.dtype = "f32"
             log(f"workload clusters16M f32: {arrs[0].size} agents")
         sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True,
-                                     backward=args.backward)
+                                     backward=args.backward, sorted_state=args.order == "sorted")
         log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
         if args.probe_copy:
             nbytes = args.probe_copy << 20
@@ -515,13 +632,17 @@ def main():
                 f"{force_source_hash()}")
         return
 
-    # headline: graph-replayed steps
-    sec, _, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True)
+    # headline: graph-replayed rollout steps on the box-sorted state
+    sorted_head = args.order == "sorted"
+    sec, _, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
+                               sorted_state=sorted_head)
     head_tuning = ws.tuning
     value = N * args.steps / sec
-    log(f"graph {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, {value:.3e} agent-steps/s")
+    log(f"graph {args.steps} steps ({args.order} state): {sec * 1e3 / args.steps:.3f} ms/step, "
+        f"{value:.3e} agent-steps/s")
     # roofline of the force kernel: eager pass with events around each launch
-    sec_e, force_ms, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True)
+    sec_e, force_ms, ws, t = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True,
+                                        sorted_state=sorted_head)
     log(f"eager {args.steps} steps: {sec_e * 1e3 / args.steps:.3f} ms/step, force kernel {force_ms * 1e3:.1f} us")
     ms.grid_build(ws, *t)
     st = workload_stats(ms, ws, N)
@@ -532,13 +653,21 @@ def main():
     flops = flops_agent * N
     peak = FP32_PEAK if args.dtype == "f32" else FP64_PEAK
     achieved = flops / (force_ms * 1e-3)
-    fb = force_bytes(N, st["n_boxes"], S)
+    fb = force_bytes(N, st["n_boxes"], S, sorted_head)
+    prof = f"{name}_{args.dtype}" + ("_sorted" if sorted_head else "")
+    issue = issue_from_profiles(prof)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                    frac=achieved / peak, traffic=traffic_from_profiles(f"{name}_{args.dtype}"),
-                    kernel="ms_mech_step = k_force + k_soa (the timed rollout step runs k_soa_integrate)", flops_per_agent=flops_agent,
+                    frac=achieved / peak, traffic=traffic_from_profiles(prof),
+                    kernel=("k_force (ms_mech_step_integrate_sorted: gather, Eq. 1, displacement "
+                            "and the state after the step in slot order)") if sorted_head else
+                    "ms_mech_step = k_force + k_soa", flops_per_agent=flops_agent,
                     force_us=force_ms * 1e3,
                     force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9,
-                    issue=issue_from_profiles(f"{name}_{args.dtype}"))
+                    force_hbm_frac=fb / (force_ms * 1e-3) / HBM_PEAK,
+                    issue=issue,
+                    bound_evidence=("VALU issue and texture units busy (rocprofv3 counters); the "
+                                    "force step's algorithmic bytes move at force_hbm_frac of HBM")
+                    if issue else None)
     balg = bytes_alg(N, st["n_boxes"], S)
     hbm = dict(step_alg_bytes=balg, step_alg_GBps=balg * args.steps / sec / 1e9,
                frac_of_peak=balg * args.steps / sec / HBM_PEAK)
@@ -547,42 +676,53 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        def plain(a, dt, **kw):
+            sx, _, wx, _ = time_plain(ms, torch, a, dt, args.steps, args.warmup, graph=True,
+                                      sorted_state=sorted_head, **kw)
+            return a[0].size * args.steps / sx, sx / args.steps * 1e3, wx.tuning["choice"]
+
         other = "f64" if args.dtype == "f32" else "f32"
         oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
-        s2, _, w2, _ = time_plain(ms, torch, oarrs, other, args.steps, args.warmup, graph=True)
-        extras[f"plain_{other}_n{args.neighbors:g}"] = N * args.steps / s2
-        extras[f"plain_{other}_n{args.neighbors:g}_gather_list"] = w2.tuning["choice"]
+        v, _, lst_ = plain(oarrs, other)
+        extras[f"plain_{other}_n{args.neighbors:g}"] = v
+        extras[f"plain_{other}_n{args.neighbors:g}_gather_list"] = lst_
+        del oarrs
         for nb in (4.0, 30.0):
             p2 = workloads.uniform(N, mean_neighbors=nb, seed=args.seed)
             a2 = [a.astype(np_in) for a in p2.arrays()]
-            s3, _, w3, _ = time_plain(ms, torch, a2, args.dtype, args.steps, args.warmup, graph=True)
-            extras[f"plain_{args.dtype}_n{nb:g}"] = N * args.steps / s3
-            extras[f"plain_{args.dtype}_n{nb:g}_gather_list"] = w3.tuning["choice"]
+            v, _, lst_ = plain(a2, args.dtype)
+            extras[f"plain_{args.dtype}_n{nb:g}"] = v
+            extras[f"plain_{args.dtype}_n{nb:g}_gather_list"] = lst_
+        # the same step with the state kept in the caller's order
+        sc, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
+                                 sorted_state=not sorted_head)
+        extras["caller_order" if sorted_head else "sorted_state"] = N * args.steps / sc
         # clustered workload: 16,777,216 agents in 64 Gaussian clusters, FP32
         cl = workloads.workload("clusters16M", seed=args.seed)
         carrs = [a.astype(np.float32) for a in cl.arrays()]
         del cl
-        s5, _, w5, _ = time_plain(ms, torch, carrs, "f32", args.steps, args.warmup, graph=True)
-        extras["clusters16M_f32"] = carrs[0].size * args.steps / s5
-        extras["clusters16M_f32_gather_list"] = w5.tuning["choice"]
-        del w5
-        extras["clusters16M_f32_ms_per_step"] = s5 / args.steps * 1e3
+        v, msps, lst_ = plain(carrs, "f32")
+        extras["clusters16M_f32"] = v
+        extras["clusters16M_f32_gather_list"] = lst_
+        extras["clusters16M_f32_ms_per_step"] = msps
         del carrs
         torch.cuda.empty_cache()
-        sorted_state = time_sorted_state(ms, torch, arrs, args.dtype, args.steps, args.warmup)
         host_state = time_host_state(ms, torch, arrs, args.steps, args.warmup) \
             if args.dtype == "f32" else None
         growing = time_growing(ms, torch, args.steps, seed=args.seed)
         s4, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
                                  backward=True)
         fwd_bwd = dict(value=N * args.steps / s4, unit="agent-steps/s", ms_per_step=s4 / args.steps * 1e3,
-                       what="grid build + forward + backward + integrate, same workload")
-        batched = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup)
-        log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; batched {batched['value']:.3e}; "
-            f"sorted state {sorted_state['value']:.3e} (reorder {sorted_state['reorder_us']:.1f} us); "
-            f"host state {host_state}; growing {growing}")
+                       what="grid build + forward + backward + integrate, same workload, caller order "
+                            "(the gradients are in the caller's order)")
+        rollout_grad = time_rollout_grad(ms, torch, args.dtype)
+        batched = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup, sorted_state=sorted_head)
+        batched["other_order_value"] = time_batched(ms, torch, max(args.steps // 2, 2), args.warmup,
+                                                    sorted_state=not sorted_head)["value"]
+        log(f"variants {extras}; fwd+bwd {fwd_bwd['value']:.3e}; rollout grad {rollout_grad['value']:.3e}; "
+            f"batched {batched['value']:.3e}; host state {host_state}; growing {growing}")
     else:
-        fwd_bwd = batched = sorted_state = host_state = growing = None
+        fwd_bwd = batched = host_state = growing = rollout_grad = None
 
     cpu = None
     if not args.no_cpu:
@@ -594,14 +734,16 @@ def main():
         "metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": name, "n_agents": N, "mean_neighbors_target": args.neighbors,
+        "config": {"workload": name, "state_order": "box-sorted slot order of each build (kept "
+                   "across the rollout)" if sorted_head else "caller order",
+                   "n_agents": N, "mean_neighbors_target": args.neighbors,
                    "measured_neighbors": st["neighbors"], "contacts_per_agent": K,
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True,
                    "gather_list": head_tuning["choice"], "gather_list_ms": head_tuning["ms"]},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
-        "variants": extras, "fwd_bwd": fwd_bwd, "batched": batched, "sorted_state": sorted_state,
-        "host_state": host_state, "growing_population": growing,
+        "variants": extras, "fwd_bwd": fwd_bwd, "rollout_grad_adjoint262k": rollout_grad,
+        "batched": batched, "host_state": host_state, "growing_population": growing,
     }
     print(json.dumps(rec), flush=True)
 

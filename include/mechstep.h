@@ -225,6 +225,43 @@ ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_para
                                            void* pby, void* pbz, void* dbar, double* g_params,
                                            void* stream);
 
+/* One rollout step on the box-sorted state (the agent sorting of Section
+ * IV-D, kept across a rollout): the step of ms_mech_step_integrate, but the
+ * state after the step is written to new arrays in the slot order of the
+ * build (agent perm[k] at k, the order ms_reorder applies: ascending box,
+ * x-quarter inside the box, input index), so every store of the step is
+ * coalesced and the next build reads nearly sorted input.
+ *   x_out, y_out, z_out [n]  positions after the step (p + Delta, rounded as
+ *                            ms_mech_step_integrate rounds them), slot order
+ *   d_out [n]                the diameters, slot order (for MS_F32 and MS_F64
+ *                            twice the build's stored radius, which is d for
+ *                            every normal d)
+ *   dx, dy, dz               NULL, or [n] displacements in slot order
+ *   x, y, z, d               the build's inputs: read (MS_F32_POS64 only) for
+ *                            the FP64 positions and diameters; may be NULL in
+ *                            the other modes
+ * Types as for ms_mech_step_integrate.  Outputs must not overlap each other or
+ * the inputs.  Other per-agent arrays of the caller follow with ms_reorder on
+ * the same build.  The first such step from a caller-order state equals
+ * ms_mech_step_integrate renumbered, bit for bit; after that the state's new
+ * numbering changes the order in which a box's agents are summed (ascending
+ * input index inside a box), so a sorted rollout agrees with the caller-order
+ * rollout to rounding, step by step within the same acceptance bound.  On a
+ * device error of the build nothing is written.
+ * Stream-ordered; allocates nothing. */
+ms_status ms_mech_step_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+                                        const void* x, const void* y, const void* z, const void* d,
+                                        void* x_out, void* y_out, void* z_out, void* d_out,
+                                        void* dx, void* dy, void* dz, void* stream);
+
+/* The same for every simulation of the last batched build (params: device
+ * ms_params [B]); agents of each simulation stay in its offset range. */
+ms_status ms_mech_step_batched_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+                                                const void* x, const void* y, const void* z,
+                                                const void* d, void* x_out, void* y_out,
+                                                void* z_out, void* d_out, void* dx, void* dy,
+                                                void* dz, void* stream);
+
 /* ms_mech_step_backward per simulation; g_params: device double [2B]. */
 ms_status ms_mech_step_backward_batched(const ms_workspace* ws, const ms_params* params,
                                         const void* gdx, const void* gdy, const void* gdz,

@@ -25,6 +25,7 @@ __all__ = [
     "Workspace", "BatchSpec", "grid_build", "mech_step", "mech_step_backward",
     "grid_build_batched", "mech_step_batched", "mech_step_backward_batched", "integrate",
     "mech_step_backward_accumulate", "mech_step_backward_batched_accumulate", "MAX_BOXES",
+    "mech_step_integrate_sorted", "mech_step_batched_integrate_sorted",
     "mech_step_integrate", "mech_step_batched_integrate",
     "reorder", "grid_info", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
     "params_tensor",
@@ -187,6 +188,45 @@ def mech_step_integrate(ws: Workspace, params, x, y, z, out=None):
     _lib.check(ws.lib.ms_mech_step_integrate(ctypes.byref(ws.c), ctypes.byref(p), _ptr(x), _ptr(y),
                                              _ptr(z), *(_ptr(a) for a in d), _stream(ws.device)))
     return out
+
+
+def _sorted_outs(ws, n, state_out, disp_out):
+    if state_out is None:
+        state_out = tuple(torch.empty(n, dtype=ws.in_dtype, device=ws.device) for _ in range(4))
+    else:
+        _check_in(ws, *state_out, n=n)
+    d = (None, None, None) if disp_out is None else _outs(ws, n, disp_out, ws.device)
+    return state_out, d
+
+
+def mech_step_integrate_sorted(ws: Workspace, params, x, y, z, d, state_out=None, disp_out=None):
+    """One rollout step on the box-sorted state: returns (x', y', z', d'), the
+    positions after the step and the diameters in the slot order of the last
+    plain build (renumbered as :func:`reorder` renumbers).  x, y, z, d are the
+    build's inputs (read only in the mixed mode).  state_out / disp_out: optional
+    preallocated outputs; disp_out receives the displacements in slot order."""
+    n = ws.n_agents
+    _check_in(ws, x, y, z, d, n=n)
+    so, dd = _sorted_outs(ws, n, state_out, disp_out)
+    p = _params(params)
+    _lib.check(ws.lib.ms_mech_step_integrate_sorted(
+        ctypes.byref(ws.c), ctypes.byref(p), *(_ptr(a) for a in (x, y, z, d)), *(_ptr(a) for a in so),
+        *(_ptr(a) for a in dd), _stream(ws.device)))
+    return so
+
+
+def mech_step_batched_integrate_sorted(ws: Workspace, params_dev, x, y, z, d, state_out=None,
+                                       disp_out=None):
+    """mech_step_integrate_sorted for every simulation of the last batched build."""
+    n = ws.n_agents
+    if params_dev.shape != (ws.n_sims, 5) or params_dev.dtype != torch.float64:
+        raise ValueError(f"params must be float64 [{ws.n_sims}, 5]")
+    _check_in(ws, x, y, z, d, n=n)
+    so, dd = _sorted_outs(ws, n, state_out, disp_out)
+    _lib.check(ws.lib.ms_mech_step_batched_integrate_sorted(
+        ctypes.byref(ws.c), _ptr(params_dev), *(_ptr(a) for a in (x, y, z, d)),
+        *(_ptr(a) for a in so), *(_ptr(a) for a in dd), _stream(ws.device)))
+    return so
 
 
 def mech_step_backward(ws: Workspace, params, gdx, gdy, gdz, out=None, g_params=None):

@@ -22,6 +22,7 @@ EXPORTS = (
     "ms_mech_step_backward", "ms_grid_build_batched", "ms_mech_step_batched",
     "ms_mech_step_backward_batched", "ms_mech_step_integrate", "ms_mech_step_batched_integrate",
     "ms_mech_step_backward_accumulate", "ms_mech_step_backward_batched_accumulate",
+    "ms_mech_step_integrate_sorted", "ms_mech_step_batched_integrate_sorted",
     "ms_integrate", "ms_reorder", "ms_grid_get", "ms_neighbors",
     "ms_device_status", "ms_copy_probe", "ms_last_error",
 )
@@ -81,6 +82,8 @@ def load():
         "ms_mech_step_backward_accumulate": (ctypes.c_int, [WS, PAR, P, P, P, P, P, P]),
         "ms_mech_step_backward_batched_accumulate": (ctypes.c_int, [WS, P, P, P, P, P, P, P]),
         "ms_mech_step_integrate": (ctypes.c_int, [WS, PAR, P, P, P, P, P, P, P]),
+        "ms_mech_step_integrate_sorted": (ctypes.c_int, [WS, PAR] + [P] * 12),
+        "ms_mech_step_batched_integrate_sorted": (ctypes.c_int, [WS, P] + [P] * 12),
         "ms_mech_step_batched_integrate": (ctypes.c_int, [WS, P, P, P, P, P, P, P, P]),
         "ms_integrate": (ctypes.c_int, [P, P, P, P, P, P, I64, ctypes.c_int, P]),
         "ms_reorder": (ctypes.c_int, [WS, P, P, I32, P]),

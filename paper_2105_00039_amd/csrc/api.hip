@@ -230,6 +230,68 @@ ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, voi
                      who);
 }
 
+// The sorted-state step: arguments checked, then the force kernel writes the
+// state after the step in slot order.
+static ms_status step_sorted_common(const ms_workspace* ws, bool batched, const ms_params* p,
+                                    const void* x, const void* y, const void* z, const void* d,
+                                    void* xo, void* yo, void* zo, void* dout, void* dx, void* dy,
+                                    void* dz, void* stream, const char* who)
+{
+    ms_status st = step_common(ws, batched ? 2 : 1, who);
+    if (st) return st;
+    if (batched) {
+        if (!p || !aligned(p, 8)) return fail(MS_EINVAL, "%s: null or misaligned params", who);
+    } else if ((st = check_params(p, who))) {
+        return st;
+    }
+    const int64_t n = ws->n_agents;
+    if (n == 0) return ok();
+    const size_t ib = in_size(ws->dtype);
+    if ((st = check_arrays(who, ib, {xo, yo, zo, dout}))) return st;
+    const bool mixed = ws->dtype == MS_F32_POS64;
+    if (mixed && (st = check_arrays(who, ib, {x, y, z, d}))) return st;
+    const int nd = (dx != nullptr) + (dy != nullptr) + (dz != nullptr);
+    if (nd != 0 && nd != 3) return fail(MS_EINVAL, "%s: dx, dy, dz must all be given or all NULL", who);
+    if (nd == 3 && (st = check_arrays(who, out_size(ws->dtype), {dx, dy, dz}))) return st;
+    // outputs must not overlap each other or the inputs
+    const uintptr_t len = (uintptr_t)n * ib;
+    const void* outs[4] = {xo, yo, zo, dout};
+    const void* all[8] = {xo, yo, zo, dout, x, y, z, d};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 8; ++b) {
+            if (a == b || !all[b]) continue;
+            const uintptr_t u = reinterpret_cast<uintptr_t>(outs[a]), v = reinterpret_cast<uintptr_t>(all[b]);
+            if (u < v + len && v < u + len) return fail(MS_EINVAL, "%s: output arrays overlap", who);
+        }
+    ms::SortedState so{xo, yo, zo, dout, x, y, z, d};
+    const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
+    return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
+                                      batched, batched ? nullptr : p, batched ? p : nullptr, dx, dy,
+                                      dz, nullptr, nullptr, nullptr,
+                                      !batched && ws->keep_forces != 0, gather_list(ws),
+                                      as_stream(stream), &so),
+                     who);
+}
+
+ms_status ms_mech_step_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+                                        const void* x, const void* y, const void* z, const void* d,
+                                        void* x_out, void* y_out, void* z_out, void* d_out,
+                                        void* dx, void* dy, void* dz, void* stream)
+{
+    return step_sorted_common(ws, false, params, x, y, z, d, x_out, y_out, z_out, d_out, dx, dy, dz,
+                              stream, "ms_mech_step_integrate_sorted");
+}
+
+ms_status ms_mech_step_batched_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+                                                const void* x, const void* y, const void* z,
+                                                const void* d, void* x_out, void* y_out,
+                                                void* z_out, void* d_out, void* dx, void* dy,
+                                                void* dz, void* stream)
+{
+    return step_sorted_common(ws, true, params, x, y, z, d, x_out, y_out, z_out, d_out, dx, dy, dz,
+                              stream, "ms_mech_step_batched_integrate_sorted");
+}
+
 ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, void* dx, void* dy,
                                void* dz, void* stream)
 {

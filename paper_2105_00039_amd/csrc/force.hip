@@ -7,16 +7,33 @@
 // candidate loads are served by L1/L2.  The force is summed in registers in
 // ascending (box, quarter, input index) order; the displacement is stored at
 // the agent's input position through perm (as one record, split by k_soa).
+// In the sorted-state step (SORTED) the kernel instead writes the agent's
+// position after the step and its diameter at its own slot, so every store
+// is coalesced and no split pass follows: the state comes out renumbered in
+// the build's slot order (the agent sorting of Section IV-D, kept across a
+// rollout).
 #include "gather.hpp"
 #include "launch.hpp"
 
 namespace ms {
 namespace {
 
+// Outputs of the sorted-state step, all in slot order: the state after the
+// step (positions and diameters of the caller's type In) and, when dx is
+// non-null, the displacements (Real).  xi..di: the build's inputs, read
+// (through perm) only where the payload does not hold them exactly, i.e. the
+// FP64 master positions and diameters of MS_F32_POS64.
+template <typename In, typename Real>
+struct SortedOut {
+    In *x, *y, *z, *d;
+    Real *dx, *dy, *dz;
+    const In *xi, *yi, *zi, *di;
+};
+
 // Plain FP64 builds ask for at least 4 wavefronts per SIMD (at most 128
 // VGPRs, against 131 otherwise): with 3 the gather's loads are hidden worse
 // (force kernel at 2M agents, n~12: 309 -> 287 us).
-template <int M, bool BATCHED, int LIST>
+template <int M, bool BATCHED, int LIST, bool SORTED>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
                                                   const int32_t* __restrict__ start,
@@ -29,9 +46,11 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
                                                   Header* __restrict__ hdr,
                                                   typename Mode<M>::Pay* __restrict__ dout,
                                                   typename Mode<M>::Pay* __restrict__ fsave,
-                                                  const F4* __restrict__ pay32)
+                                                  const F4* __restrict__ pay32,
+                                                  SortedOut<typename Mode<M>::In, typename Mode<M>::Real> so)
 {
     using Real = typename Mode<M>::Real;
+    using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
     // plain FP64 builds scan their FP32 slot copy
     constexpr bool PRE = M == MS_F64 && !BATCHED;
@@ -63,10 +82,28 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     }
     Real ddx, ddy, ddz;
     displacement<Real>(fx, fy, fz, (Real)P.dt, (Real)P.max_disp, (Real)P.adherence, ddx, ddy, ddz);
-    const int32_t o = perm[k];
-    Pay v;
-    v.x = ddx; v.y = ddy; v.z = ddz; v.w = (Real)0;
-    dout[o] = v;
+    if constexpr (SORTED) {
+        // p + Delta as k_soa_integrate forms it (Delta converted to In, then
+        // added): the step equals the caller-order step renumbered
+        In px, py, pz, pd;
+        if constexpr (M == MS_F32_POS64) {
+            const int32_t o = perm[k];
+            px = so.xi[o]; py = so.yi[o]; pz = so.zi[o]; pd = so.di[o];
+        } else {
+            px = pi.x; py = pi.y; pz = pi.z;
+            pd = (In)2 * pi.w;   // the build stored d/2: exact for every normal d
+        }
+        so.x[k] = px + (In)ddx;
+        so.y[k] = py + (In)ddy;
+        so.z[k] = pz + (In)ddz;
+        so.d[k] = pd;
+        if (so.dx) { so.dx[k] = ddx; so.dy[k] = ddy; so.dz[k] = ddz; }
+    } else {
+        const int32_t o = perm[k];
+        Pay v;
+        v.x = ddx; v.y = ddy; v.z = ddz; v.w = (Real)0;
+        dout[o] = v;
+    }
 }
 
 // The force kernel stores each displacement as one 16-byte (FP64: 32-byte)
@@ -263,38 +300,63 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
     for (; i < n4; i += stride) dst[i] = src[i];
 }
 
+template <int M, bool BATCHED, int LIST, bool SORTED>
+void launch_k_force(const Dev& D, int64_t n, int32_t B, const ms_params& p1, const ms_params* p_dev,
+                    typename Mode<M>::Pay* rec, typename Mode<M>::Pay* fs,
+                    const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, hipStream_t s)
+{
+    using Pay = typename Mode<M>::Pay;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_force<M, BATCHED, LIST, SORTED><<<nb, kBlock, 0, s>>>(
+        static_cast<const Pay*>(D.payload), D.start, D.split, D.perm, D.geom, BATCHED ? D.off : nullptr,
+        B, n, p1, p_dev, D.hdr, rec, fs, D.pay32, so);
+}
+
+template <int M, bool SORTED>
+void launch_k_force_list(const Dev& D, int64_t n, int32_t B, bool batched, const ms_params& p1,
+                         const ms_params* p_dev, typename Mode<M>::Pay* rec,
+                         typename Mode<M>::Pay* fs,
+                         const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, int list,
+                         hipStream_t s)
+{
+    if (batched && list == kLongList)
+        launch_k_force<M, true, kLongList, SORTED>(D, n, B, p1, p_dev, rec, nullptr, so, s);
+    else if (batched)
+        launch_k_force<M, true, kMaxContacts, SORTED>(D, n, B, p1, p_dev, rec, nullptr, so, s);
+    else if (list == kLongList)
+        launch_k_force<M, false, kLongList, SORTED>(D, n, 1, p1, nullptr, rec, fs, so, s);
+    else
+        launch_k_force<M, false, kMaxContacts, SORTED>(D, n, 1, p1, nullptr, rec, fs, so, s);
+}
+
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                      void* dz, void* px, void* py, void* pz, bool keep, int list, hipStream_t s)
+                      void* dz, void* px, void* py, void* pz, bool keep, int list,
+                      const SortedState* sorted, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
+    using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    const Pay* pay = static_cast<const Pay*>(D.payload);
     Real* X = static_cast<Real*>(dx);
     Real* Y = static_cast<Real*>(dy);
     Real* Z = static_cast<Real*>(dz);
     Pay* A = static_cast<Pay*>(D.pay2);
-    Pay* fs = keep ? static_cast<Pay*>(D.fsave) : nullptr;
-    ms_params dummy{};
-    if (batched && list == kLongList)
-        k_force<M, true, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off,
-                                                           B, n, dummy, p_dev, D.hdr, A, nullptr, D.pay32);
-    else if (batched)
-        k_force<M, true, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
-                                                              D.off, B, n, dummy, p_dev, D.hdr, A,
-                                                              nullptr, D.pay32);
-    else if (list == kLongList)
-        k_force<M, false, kLongList><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
-                                                            nullptr, 1, n, *p_host, nullptr, D.hdr,
-                                                            A, fs, D.pay32);
-    else
-        k_force<M, false, kMaxContacts><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom,
-                                                               nullptr, 1, n, *p_host, nullptr,
-                                                               D.hdr, A, fs, D.pay32);
+    Pay* fs = (keep && !batched) ? static_cast<Pay*>(D.fsave) : nullptr;
+    const ms_params p1 = batched ? ms_params{} : *p_host;
+    SortedOut<In, Real> so{};
+    if (sorted) {
+        so.x = static_cast<In*>(sorted->x_out); so.y = static_cast<In*>(sorted->y_out);
+        so.z = static_cast<In*>(sorted->z_out); so.d = static_cast<In*>(sorted->d_out);
+        so.dx = X; so.dy = Y; so.dz = Z;
+        so.xi = static_cast<const In*>(sorted->x_in); so.yi = static_cast<const In*>(sorted->y_in);
+        so.zi = static_cast<const In*>(sorted->z_in); so.di = static_cast<const In*>(sorted->d_in);
+        launch_k_force_list<M, true>(D, n, B, batched, p1, p_dev, A, fs, so, list, s);
+        return hipGetLastError();
+    }
+    launch_k_force_list<M, false>(D, n, B, batched, p1, p_dev, A, fs, so, list, s);
     if (px) {
-        using In = typename Mode<M>::In;
         k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),
                                                              static_cast<In*>(py),
                                                              static_cast<In*>(pz));
@@ -343,18 +405,18 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
                         void* dz, void* px, void* py, void* pz, bool keep, int list,
-                        hipStream_t s)
+                        hipStream_t s, const SortedState* sorted)
 {
     switch (L.dtype) {
     case MS_F32:
         return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, s);
+                                  list, sorted, s);
     case MS_F64:
         return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, s);
+                                  list, sorted, s);
     case MS_F32_POS64:
         return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz,
-                                        keep, list, s);
+                                        keep, list, sorted, s);
     default: return hipErrorInvalidValue;
     }
 }

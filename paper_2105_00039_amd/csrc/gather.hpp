@@ -111,7 +111,10 @@ __device__ __forceinline__ Real len2(Real ux, Real uy, Real uz)
 
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
-// a reciprocal.
+// a reciprocal.  Each pair's term is rounded before it is added (multiply,
+// then add): two pairs that mirror each other then cancel exactly, as the
+// oracle's do (a fused multiply-add would leave the rounding error of the
+// first product behind).
 __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float kap, float gam,
                                               float& ax, float& ay, float& az)
 {
@@ -124,9 +127,9 @@ __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float k
         const float rho = pi.w * q.w * __builtin_amdgcn_rcpf(rs);
         const float sv = fmad(kap, delta, -gam * __builtin_amdgcn_sqrtf(rho * delta));
         const float sl = sv * il;
-        ax = fmad(sl, ux, ax);
-        ay = fmad(sl, uy, ay);
-        az = fmad(sl, uz, az);
+        ax += sl * ux;
+        ay += sl * uy;
+        az += sl * uz;
     }
 }
 
@@ -142,9 +145,9 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
         const double rho = pi.w * q.w / rs;
         const double sv = fmad(kap, delta, -gam * sqrt(rho * delta));
         const double sl = sv / l;
-        ax = fmad(sl, ux, ax);
-        ay = fmad(sl, uy, ay);
-        az = fmad(sl, uz, az);
+        ax += sl * ux;
+        ay += sl * uy;
+        az += sl * uz;
     }
 }
 

@@ -18,14 +18,24 @@ hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const
 // D.canon / D.cslot, for the exports.
 hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s);
 
+// Sorted-state step: the state after the step (positions + Delta and the
+// diameters) written in the build's slot order to *_out; *_in are the build's
+// inputs (read only in MS_F32_POS64 mode).
+struct SortedState {
+    void *x_out, *y_out, *z_out, *d_out;
+    const void *x_in, *y_in, *z_in, *d_in;
+};
+
 // Forward step.  Single: p_host valid, off == nullptr.  Batched: p_dev valid.
 // px/py/pz non-null: positions updated in place (p += Delta); dx/dy/dz may
-// then be null.  keep (single only): also store the forces for the backward
-// step.  list: contact-list length of the gather (kMaxContacts or kLongList).
+// then be null.  sorted non-null: the sorted-state step (dx/dy/dz, if given,
+// in slot order; px/py/pz unused).  keep (single only): also store the
+// forces for the backward step.  list: contact-list length of the gather
+// (kMaxContacts or kLongList).
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
                         void* dz, void* px, void* py, void* pz, bool keep, int list,
-                        hipStream_t s);
+                        hipStream_t s, const SortedState* sorted = nullptr);
 
 // Backward step; list: contact-list length of its gathers (as launch_force).
 // acc: rollout mode, gdx..gdz == gx..gz are the position gradients of the

@@ -61,11 +61,21 @@ def _case(name):
                 r.uniform(8, 12, 4500))
     if name == "two":
         return np.array([0.0, 9.0]), np.zeros(2), np.zeros(2), np.array([10.0, 10.0])
+    if name == "touching3":
+        # W3: agents 0 and 1 exactly touching (delta = 0), 1 and 2 apart by 0.5
+        return np.array([0.0, 10.0, 20.5]), np.zeros(3), np.zeros(3), np.full(3, 10.0)
+    if name == "coincident3":
+        # W7: agents 0 and 1 at the same point, both in W1 contact with agent 2
+        return np.array([0.0, 0.0, 9.0]), np.zeros(3), np.zeros(3), np.full(3, 10.0)
+    if name == "lattice_exact":
+        # W6 on the full 16^3 lattice: spacing 9, no jitter, d = 10
+        return workloads.lattice(jitter=0.0, dmin=10.0, dmax=10.0).arrays()
     raise KeyError(name)
 
 
 CASES = ["lattice4096", "uniform10007_n12", "uniform5003_n30", "uniform3001_n4", "clusters20000",
-         "collinear999", "one_box777", "dense_cluster30000", "one_box4500", "two"]
+         "collinear999", "one_box777", "dense_cluster30000", "one_box4500", "two", "touching3",
+         "coincident3", "lattice_exact"]
 # box capacity where the default (4 per agent + 4096) is too small
 CASE_MAX_BOXES = {"dense_cluster30000": 400_000}
 
@@ -136,6 +146,38 @@ def test_force_and_displacement_parity(case, mode):
     _, Do = oracle.step(*o, P)
     bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
     check_vectors(D, Do, bound, f"displacement {case} {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_exact_cases_of_eq1(mode):
+    """The closed-form cases of Eq. 1 that have exact answers: a touching
+    pair adds nothing (exactly 0 on the FP64 path; on the FP32 paths the
+    rounding of |p1 - p2| may open a contact of order sqrt(u), which the onset
+    allowance bounds), coincident centres add nothing, and on the unjittered
+    lattice every interior agent's face contacts cancel exactly while a face
+    agent gets the W1 force along its outward normal."""
+    # touching pair (W3)
+    arrs = _case("touching3")
+    _, F = step(arrs, mode, P_FORCE)
+    if mode == "f64":
+        assert np.all(F == 0)
+    else:
+        S, A, _ = oracle.tolerance_scales(*oracle_inputs(arrs, mode), 2.0, 1.0, UNIT[mode])
+        assert np.all(np.linalg.norm(F, axis=1) <= A) and np.all(F[2] == 0)
+    # coincident centres (W7): each of the pair only feels agent 2
+    _, F = step(_case("coincident3"), mode, P_FORCE)
+    s1 = 2.0 - np.sqrt(2.5)
+    tol = 1e-12 if mode == "f64" else 1e-5
+    np.testing.assert_allclose(F[:, 0], [-s1, -s1, 2 * s1], rtol=tol, atol=0)
+    assert np.all(F[:, 1:] == 0)
+    # unjittered lattice (W6)
+    arrs = _case("lattice_exact")
+    _, F = step(arrs, mode, P_FORCE)
+    idx = np.rint(np.stack(arrs[:3], axis=1) / 9.0).astype(int)
+    interior = np.all((idx > 0) & (idx < 15), axis=1)
+    assert interior.sum() == 14 ** 3 and np.all(F[interior] == 0)
+    want = np.where(idx == 0, -s1, np.where(idx == 15, s1, 0.0))
+    np.testing.assert_allclose(F[~interior], want[~interior], rtol=tol, atol=0)
 
 
 @pytest.mark.parametrize("mode", MODES)
