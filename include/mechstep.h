@@ -319,6 +319,31 @@ ms_status ms_neighbors(const ms_workspace* ws, int32_t* counts, int64_t* offsets
  * MS_OK, MS_EINPUT, MS_EINVAL or MS_ECAPACITY. */
 ms_status ms_device_status(const ms_workspace* ws, void* stream);
 
+/* ms_grid_build followed by ms_mech_step without any allocation and without a
+ * caller workspace, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The grid lives in a workspace the library keeps in a static
+ * device array of about 18 MB, one copy per GPU, held until the process ends
+ * (its address is looked up once per device, on the first call there).
+ *   x, y, z, d  [n] inputs of `dtype` as for ms_grid_build; edge as there
+ *   p           host parameters as for ms_mech_step
+ *   dx, dy, dz  [n] displacements (caller order), as ms_mech_step writes them
+ *   dev_error   NULL, or one device int32 that receives the build's device
+ *               error bits (0 = fine; 1, 2 bad input, 4 bad edge, 8 more
+ *               than MS_NOALLOC_MAX_BOXES boxes), written on `stream` after
+ *               the step; on an error the displacements are unspecified.
+ * n above MS_NOALLOC_MAX_AGENTS returns MS_ECAPACITY at once.  Results equal
+ * ms_grid_build + ms_mech_step (default contact list, keep_forces 0) bit for
+ * bit.  Every call on one GPU uses that GPU's single array and leaves its
+ * contents behind for the next: calls that overlap on one GPU (different
+ * streams or host threads without ordering) race and give wrong results.
+ * Stream-ordered; makes no hipMalloc, hipFree or other allocating call. */
+#define MS_NOALLOC_MAX_AGENTS 65536
+#define MS_NOALLOC_MAX_BOXES 524288
+ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, const void* d,
+                               int64_t n, ms_dtype dtype, double edge, const ms_params* p,
+                               void* dx, void* dy, void* dz, int32_t* dev_error, void* stream);
+
 /* Streaming copy of `bytes` bytes (multiple of 16) from src to dst: the
  * bandwidth probe used as the empirical HBM roof. */
 ms_status ms_copy_probe(void* dst, const void* src, size_t bytes, void* stream);

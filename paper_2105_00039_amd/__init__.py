@@ -28,7 +28,7 @@ __all__ = [
     "mech_step_integrate_sorted", "mech_step_batched_integrate_sorted",
     "mech_step_integrate", "mech_step_batched_integrate",
     "reorder", "grid_info", "grid_get", "neighbors", "device_status", "copy_probe", "MechStepError",
-    "params_tensor",
+    "params_tensor", "mech_step_noalloc",
 ]
 
 _DTYPES = {
@@ -403,6 +403,34 @@ def neighbors(ws: Workspace):
     _lib.check(ws.lib.ms_neighbors(ctypes.byref(ws.c), _ptr(counts), _ptr(offsets), _ptr(lst),
                                    lst.numel(), ctypes.byref(total), _stream(ws.device)))
     return counts[:n], offsets, lst[: total.value]
+
+
+def mech_step_noalloc(x, y, z, d, params, dtype: str = "f32", edge: float = 0.0, out=None,
+                      dev_error=None):
+    """Grid build + one step on the library's static workspace (no allocation
+    inside the library; at most NOALLOC_MAX_AGENTS agents).  out: (dx, dy, dz)
+    to fill, else allocated here; dev_error: None or a device int32 tensor of
+    one element that receives the build's device error bits."""
+    lib = _lib.load()
+    if dtype not in _DTYPES:
+        raise ValueError(f"dtype must be one of {list(_DTYPES)}")
+    code, in_dtype, out_dtype = _DTYPES[dtype]
+    n = int(x.numel())
+    for t in (x, y, z, d):
+        if t.dtype != in_dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"inputs must be contiguous {in_dtype} device tensors of equal length")
+    if out is None:
+        out = tuple(torch.empty(n, dtype=out_dtype, device=x.device) for _ in range(3))
+    for t in out:
+        if t.dtype != out_dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"outputs must be contiguous {out_dtype} device tensors of length n")
+    if dev_error is not None and (dev_error.dtype != torch.int32 or not dev_error.is_cuda):
+        raise ValueError("dev_error must be an int32 device tensor")
+    p = _params(params)
+    _lib.check(lib.ms_mech_step_noalloc(_ptr(x), _ptr(y), _ptr(z), _ptr(d), n, code, float(edge),
+                                        ctypes.byref(p), *(_ptr(t) for t in out), _ptr(dev_error),
+                                        _stream(x.device)))
+    return out
 
 
 def device_status(ws: Workspace):

@@ -24,8 +24,11 @@ EXPORTS = (
     "ms_mech_step_backward_accumulate", "ms_mech_step_backward_batched_accumulate",
     "ms_mech_step_integrate_sorted", "ms_mech_step_batched_integrate_sorted",
     "ms_integrate", "ms_reorder", "ms_grid_get", "ms_neighbors",
-    "ms_device_status", "ms_copy_probe", "ms_last_error",
+    "ms_device_status", "ms_copy_probe", "ms_last_error", "ms_mech_step_noalloc",
 )
+# capacities of ms_mech_step_noalloc's static workspace (mechstep.h)
+NOALLOC_MAX_AGENTS = 65536
+NOALLOC_MAX_BOXES = 524288
 
 
 class ms_params(ctypes.Structure):
@@ -91,6 +94,7 @@ def load():
         "ms_neighbors": (ctypes.c_int, [WS, P, P, P, I64, ctypes.POINTER(ctypes.c_int64), P]),
         "ms_device_status": (ctypes.c_int, [WS, P]),
         "ms_copy_probe": (ctypes.c_int, [P, P, SZ, P]),
+        "ms_mech_step_noalloc": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_int, D, PAR, P, P, P, P, P]),
         "ms_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

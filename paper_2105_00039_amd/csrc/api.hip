@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <vector>
 
 #include "launch.hpp"
@@ -543,6 +544,88 @@ ms_status ms_copy_probe(void* dst, const void* src, size_t bytes, void* stream)
         return fail(MS_EINVAL, "%s: pointers must be 16-byte aligned and bytes a multiple of 16", who);
     if (bytes == 0) return ok();
     return check_hip(ms::launch_copy_probe(dst, src, bytes, as_stream(stream)), who);
+}
+
+// ------------------------------------------------- the step without allocation
+
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t kNoAllocAgents = MS_NOALLOC_MAX_AGENTS;
+constexpr int64_t kNoAllocBoxes = MS_NOALLOC_MAX_BOXES;
+// The largest layout of the three modes (MS_F64 has 32-byte payloads and the
+// FP32 slot copy).
+constexpr size_t kNoAllocBytes = ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F64).total;
+static_assert(ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F32).total <= kNoAllocBytes &&
+                  ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F32_POS64).total <=
+                      kNoAllocBytes,
+              "the static workspace holds every mode");
+
+// The workspace of ms_mech_step_noalloc, one copy per GPU for the life of the
+// process.  Host code never uses this name as an address: each device's copy
+// is reached through the pointer hipGetSymbolAddress returns for it.
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device ordinal; null until first used
+
+// Device address of the current device's scratch (looked up once per device).
+ms_status scratch_address(void** out, const char* who)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MS_EDEVICE, "%s: hipGetDevice: %s", who, hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MS_EDEVICE, "%s: hipGetSymbolAddress(scratch) on device %d: %s", who, dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, const void* d, int64_t n,
+                               ms_dtype dtype, double edge, const ms_params* p, void* dx, void* dy,
+                               void* dz, int32_t* dev_error, void* stream)
+{
+    const char* who = "ms_mech_step_noalloc";
+    if (dtype < MS_F32 || dtype > MS_F32_POS64) return fail(MS_EINVAL, "%s: unknown dtype %d", who, (int)dtype);
+    if (n < 0) return fail(MS_EINVAL, "%s: n < 0", who);
+    if (n > kNoAllocAgents)
+        return fail(MS_ECAPACITY, "%s: n = %lld exceeds MS_NOALLOC_MAX_AGENTS = %lld", who,
+                    (long long)n, (long long)kNoAllocAgents);
+    ms_status st = check_params(p, who);
+    if (st) return st;
+    if (!std::isfinite(edge)) return fail(MS_EINVAL, "%s: non-finite edge", who);
+    if (dev_error && !aligned(dev_error, 4)) return fail(MS_EINVAL, "%s: dev_error not aligned", who);
+    if (n > 0) {
+        if ((st = check_arrays(who, in_size(dtype), {x, y, z, d}))) return st;
+        if ((st = check_arrays(who, out_size(dtype), {dx, dy, dz}))) return st;
+    }
+    void* base = nullptr;
+    if ((st = scratch_address(&base, who))) return st;
+    hipStream_t s = as_stream(stream);
+    const ms::Layout L = ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, dtype);
+    const ms::Dev D = ms::resolve(L, base);
+    // a fresh header for every call: the array keeps the previous call's state
+    hipError_t e = ms::launch_init(L, D, s);
+    if (e == hipSuccess && n > 0)
+        e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, s);
+    if (e == hipSuccess && n > 0)
+        e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
+                             false, ms::kMaxContacts, s);
+    if (e == hipSuccess && dev_error) e = ms::launch_error_copy(D, dev_error, s);
+    return check_hip(e, who);
 }
 
 const char* ms_last_error(void) { return g_err; }

@@ -96,9 +96,10 @@ struct Layout {
     int32_t dtype;
 };
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sims, int32_t dtype)
+constexpr Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_sims,
+                             int32_t dtype)
 {
     Layout L{};
     L.max_agents = max_agents;

@@ -71,6 +71,11 @@ __global__ void k_init(Header* hdr)
     if (threadIdx.x < sizeof(Header) / 4) reinterpret_cast<uint32_t*>(hdr)[threadIdx.x] = 0u;
 }
 
+__global__ void k_error_copy(const Header* __restrict__ hdr, int32_t* __restrict__ out)
+{
+    if (threadIdx.x == 0) out[0] = (int32_t)hdr->error;
+}
+
 // ------------------------------------------------------------- offsets copy
 
 // Copies the caller's simulation offsets into the workspace and checks that
@@ -1044,6 +1049,12 @@ hipError_t launch_init(const Layout& L, const Dev& D, hipStream_t s)
 {
     (void)L;
     k_init<<<1, 64, 0, s>>>(D.hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_error_copy(const Dev& D, int32_t* out, hipStream_t s)
+{
+    k_error_copy<<<1, 64, 0, s>>>(D.hdr, out);
     return hipGetLastError();
 }
 

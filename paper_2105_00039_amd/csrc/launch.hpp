@@ -8,6 +8,9 @@ namespace ms {
 // Clear the device state of a fresh workspace.
 hipError_t launch_init(const Layout& L, const Dev& D, hipStream_t s);
 
+// out[0] = the workspace's device error word (a one-thread kernel).
+hipError_t launch_error_copy(const Dev& D, int32_t* out, hipStream_t s);
+
 // Uniform grid: bounds -> geometry -> count -> scan -> scatter -> rank.
 // off == nullptr means one simulation of n agents (B must be 1).
 hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const void* y,

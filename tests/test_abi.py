@@ -155,3 +155,28 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liborc" not in text, f
+
+
+def test_noalloc_host_checks(lib):
+    """The step without allocation refuses more agents than its static
+    workspace holds, and bad arguments, before touching the device; the
+    header's limits are the binding's."""
+    from paper_2105_00039_amd import _lib
+    text = open(HEADER).read()
+    assert f"#define MS_NOALLOC_MAX_AGENTS {_lib.NOALLOC_MAX_AGENTS}" in text
+    assert f"#define MS_NOALLOC_MAX_BOXES {_lib.NOALLOC_MAX_BOXES}" in text
+    p = _lib.ms_params(2, 1, 0.01, 3, 0)
+    nul = ctypes.c_void_p(0)
+    st = lib.ms_mech_step_noalloc(nul, nul, nul, nul, _lib.NOALLOC_MAX_AGENTS + 1, _lib.MS_F32, 0.0,
+                                  ctypes.byref(p), nul, nul, nul, nul, nul)
+    assert st == _lib.MS_ECAPACITY
+    assert b"MS_NOALLOC_MAX_AGENTS" in lib.ms_last_error()
+    assert lib.ms_mech_step_noalloc(nul, nul, nul, nul, -1, _lib.MS_F32, 0.0, ctypes.byref(p),
+                                    nul, nul, nul, nul, nul) == _lib.MS_EINVAL
+    assert lib.ms_mech_step_noalloc(nul, nul, nul, nul, 10, 9, 0.0, ctypes.byref(p),
+                                    nul, nul, nul, nul, nul) == _lib.MS_EINVAL
+    bad = _lib.ms_params(2, 1, -0.01, 3, 0)
+    assert lib.ms_mech_step_noalloc(nul, nul, nul, nul, 10, _lib.MS_F32, 0.0, ctypes.byref(bad),
+                                    nul, nul, nul, nul, nul) == _lib.MS_EINVAL
+    assert lib.ms_mech_step_noalloc(nul, nul, nul, nul, 10, _lib.MS_F32, 0.0, ctypes.byref(p),
+                                    nul, nul, nul, nul, nul) == _lib.MS_EINVAL
