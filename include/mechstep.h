@@ -230,7 +230,10 @@ ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_para
  * state after the step is written to new arrays in the slot order of the
  * build (agent perm[k] at k, the order ms_reorder applies: ascending box,
  * x-quarter inside the box, input index), so every store of the step is
- * coalesced and the next build reads nearly sorted input.
+ * coalesced and the next build reads nearly sorted input.  The next build on
+ * the same workspace then takes each agent's position and diameter straight
+ * from its inputs instead of carrying them through its partition (faster on
+ * nearly sorted input; the build is the same for any input).
  *   x_out, y_out, z_out [n]  positions after the step (p + Delta, rounded as
  *                            ms_mech_step_integrate rounds them), slot order
  *   d_out [n]                the diameters, slot order (for MS_F32 and MS_F64
@@ -287,8 +290,10 @@ ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy
  * canonical order, ascending box then input index; both are box-sorted.)
  * Applying it to every per-agent array of the caller (positions, diameters and
  * any attributes) renumbers the agents in box order, so the next build reads
- * nearly sorted input and writes the displacements nearly in order; agents of
- * one simulation of a batched build stay inside that simulation's range.
+ * nearly sorted input and writes the displacements nearly in order (and, as
+ * after ms_mech_step_integrate_sorted, takes the payload from its inputs);
+ * agents of one simulation of a batched build stay inside that simulation's
+ * range.
  * src, dst: device arrays of n_agents elements of elem_bytes (1, 2, 4, 8 or
  * 16) bytes, aligned to elem_bytes; they must not overlap (MS_EINVAL).  The
  * caller owns both.  A device error of the last build leaves dst unwritten.

@@ -48,11 +48,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
                                                      const typename Mode<M>::Pay* __restrict__ gin,
                                                      typename Mode<M>::Pay* __restrict__ fbar,
                                                      const typename Mode<M>::Pay* __restrict__ fsave,
-                                                     const F4* __restrict__ pay32)
+                                                     const uint2* __restrict__ payq)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    constexpr bool PRE = M == MS_F64 && !BATCHED;   // plain FP64 builds scan their FP32 copy
+    constexpr bool PRE = !BATCHED;   // plain builds scan their quantised slot copy
     __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     } else {
         force_sum<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                         pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                                        pre32_of<PRE>(pay32, k, g), fx, fy, fz);
+                                        preq_of<PRE>(payq, k), fx, fy, fz);
     }
     const Pay gr = gin[perm[k]];
     const Real gx = gr.x, gy = gr.y, gz = gr.z;
@@ -171,11 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
                                                        const Header* __restrict__ hdr,
                                                        typename Mode<M>::Pay* __restrict__ gout,
                                                        double* __restrict__ partials,
-                                                       const F4* __restrict__ pay32)
+                                                       const uint2* __restrict__ payq)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    constexpr bool PRE = M == MS_F64 && !BATCHED;   // plain FP64 builds scan their FP32 copy
+    constexpr bool PRE = !BATCHED;   // plain builds scan their quantised slot copy
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
     __shared__ uint32_t lst[LIST * kBlock];
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
         scan_contacts<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start,
                                             split, pay, lst + threadIdx.x,
-                                            pre32_of<PRE>(pay32, k, g),
+                                            preq_of<PRE>(payq, k),
                                             [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
             Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
@@ -320,17 +320,17 @@ hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
                                                        (const Real*)gdz, n, D.hdr, rec);
     if (batched) {
         k_bwd_fbar<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
-                                                   dummy, p_dev, D.hdr, rec, fb, nullptr, D.pay32);
+                                                   dummy, p_dev, D.hdr, rec, fb, nullptr, D.payq);
         k_bwd_gather<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
-                                                     n, dummy, p_dev, D.hdr, rec, D.partials, D.pay32);
+                                                     n, dummy, p_dev, D.hdr, rec, D.partials, D.payq);
         k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params, acc);
     } else {
         k_bwd_fbar<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
-                                                    static_cast<const Pay*>(D.fsave), D.pay32);
+                                                    static_cast<const Pay*>(D.fsave), D.payq);
         k_bwd_gather<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
-                                                      D.partials, D.pay32);
+                                                      D.partials, D.payq);
         k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params, acc);
     }
     if (acc)

@@ -554,8 +554,7 @@ namespace {
 
 constexpr int64_t kNoAllocAgents = MS_NOALLOC_MAX_AGENTS;
 constexpr int64_t kNoAllocBoxes = MS_NOALLOC_MAX_BOXES;
-// The largest layout of the three modes (MS_F64 has 32-byte payloads and the
-// FP32 slot copy).
+// The largest layout of the three modes (MS_F64 has 32-byte payloads).
 constexpr size_t kNoAllocBytes = ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F64).total;
 static_assert(ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F32).total <= kNoAllocBytes &&
                   ms::make_layout(kNoAllocAgents, kNoAllocBoxes, 1, MS_F32_POS64).total <=

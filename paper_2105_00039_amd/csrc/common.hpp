@@ -23,6 +23,10 @@ constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
+// Quantised slot copy of plain builds (the gather's candidate test): quanta
+// per box edge, and the margin (in quanta) added to the summed radii.
+constexpr int kQuantScale = 8192;
+constexpr int kQuantMargin = 2;
 // Boxes a build can hold over all its simulations: the two-level sort keeps at
 // most kBucketsMax buckets of at most 2^kSBMax boxes.
 constexpr int64_t kMaxBoxes = (int64_t)kBucketsMax << kSBMax;
@@ -53,7 +57,9 @@ struct Header {
     uint32_t build_gen;    // incremented by every build
     uint32_t fwd_gen;      // build_gen of the forward step that kept its forces
     ms_params fwd_params;  // parameters of that forward step
-    uint8_t pad[256 - 96];
+    uint32_t gather;       // 1: the current build's partition moves keys and indices only
+    uint32_t next_sorted;  // 1: the last call wrote a state in slot order (sorted step, reorder)
+    uint8_t pad[256 - 104];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -90,7 +96,7 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
     size_t hdr, geom, off, bpart, box_id, quarter, start, split, hist, bstart, key2, idx2, pay2,
-        tmp, perm, payload, pay32, fbar, fsave, partials, scratch64, total;
+        tmp, perm, payload, payq, fbar, fsave, partials, scratch64, total;
     int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
@@ -133,9 +139,9 @@ constexpr Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_
     L.perm = take(4 * (size_t)na);
     // three extra entries: the gather reads up to three slots past a run's end
     L.payload = take(pay * (size_t)(na + 3));
-    // FP64 builds of one simulation: a 16-byte FP32 copy of each slot for the
+    // builds of one simulation: an 8-byte quantised copy of each slot for the
     // gather's candidate test (same three extra entries)
-    L.pay32 = take(dtype == MS_F64 ? sizeof(F4) * (size_t)(na + 3) : 0);
+    L.payq = take(8 * (size_t)(na + 3));
     L.fbar = take(pay * (size_t)na);
     L.fsave = take(pay * (size_t)na);
     L.partials = take(16 * (size_t)L.n_part);
@@ -156,7 +162,7 @@ struct Dev {
     int32_t* start;     // box start offsets [total boxes + 1]
     uint32_t* split;    // per box b: [2b] = start[b], [2b + 1] = quarter split word
     int32_t* hist;      // [bucket][block-A] histogram, scanned in place along each row
-    int32_t* bstart;    // [0, nb]: bucket starts; [nb_cap+1 ...]: bucket totals
+    int32_t* bstart;    // [nb_cap+1 ...]: bucket totals
     int32_t* key2;      // build: (box in bucket) << 2 | quarter, bucket order
     int32_t* idx2;      // build: input index, bucket order
     void* pay2;
@@ -168,7 +174,7 @@ struct Dev {
     int32_t* canon;
     int32_t* cslot;
     void* payload;
-    F4* pay32;          // FP64 plain builds: ((p - origin) / edge, r / edge) in FP32, slot order
+    uint2* payq;        // plain builds: quantised (x, y | z, -r) of each slot (gather.hpp)
     void* fbar;
     void* fsave;        // forces of the last forward step that kept them (slot order)
     double* partials;
@@ -197,7 +203,7 @@ inline Dev resolve(const Layout& L, void* base)
     d.canon = d.idx2;
     d.cslot = d.key2;
     d.payload = b + L.payload;
-    d.pay32 = reinterpret_cast<F4*>(b + L.pay32);
+    d.payq = reinterpret_cast<uint2*>(b + L.payq);
     d.fbar = b + L.fbar;
     d.fsave = b + L.fsave;
     d.partials = reinterpret_cast<double*>(b + L.partials);

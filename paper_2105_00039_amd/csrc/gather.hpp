@@ -61,6 +61,7 @@ __device__ __forceinline__ void pin4(Pay (&q)[4])
 }
 __device__ __forceinline__ void pin(F4& q) { asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z), "+v"(q.w)); }
 __device__ __forceinline__ void pin(D4& q) { asm volatile("" : "+v"(q.x), "+v"(q.y), "+v"(q.z), "+v"(q.w)); }
+__device__ __forceinline__ void pin(uint2& q) { asm volatile("" : "+v"(q.x), "+v"(q.y)); }
 
 // Box coordinates of a position: the same FP64 binning as the grid build.
 template <typename Real>
@@ -236,47 +237,67 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     return R;
 }
 
-// Candidate test of the FP64 path on the FP32 slot copy written by plain
-// FP64 builds (coordinates relative to the grid origin and radius, in units
-// of the box edge).  The test accepts |u| < r_i + r_j + tol; tol covers the
-// rounding of the copy (2^-24 of a coordinate, at most the box count per
-// axis) and of the FP32 test with a wide margin, so no pair in contact is
-// rejected, and the exact FP64 test of contact_force decides every accepted
-// pair.  The scan then loads 16 instead of 32 bytes per candidate.
-struct Pre32 {
-    const F4* pay32;
-    F4 pi;        // the agent's own copy
-    float tol;
+// Candidate test of plain builds on the quantised slot copy the build writes
+// (one 8-byte word pair per slot): x, y, z relative to the grid origin in
+// units of e / kQuantScale, rounded down, each kept modulo 2^16, and the
+// radius in the same units rounded up, stored negated.  A stencil candidate
+// lies within two box edges of the agent on every axis, i.e. within 2^14
+// quanta, so the 16-bit wrapped differences are the exact differences of the
+// quantised coordinates; the squares are summed exactly in 32-bit integers
+// by the packed 16-bit dot product (at most 3 * 2^28).  Each difference is
+// within one quantum of the true difference times the scale, so every pair
+// with |u| < r_i + r_j satisfies |u_q| < rq_i + rq_j + kQuantMargin: no pair
+// in contact is rejected, and the kernel's own precision decides every
+// accepted pair (delta > 0 in contact_force), so the contacts and their
+// order, hence the sums, are the same as with an exact test.  The scan then
+// loads 8 bytes per candidate instead of 16 (FP32) or 32 (FP64), and tests it
+// with five packed-integer operations.
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+
+struct PreQ {
+    const uint2* payq;
+    uint32_t axy;   // the agent's own (x, y) quanta
+    uint32_t azr;   // its z quanta and rq + kQuantMargin
 };
 
-__device__ __forceinline__ float pre32_tol(const SimGeom& g)
-{
-    const int m = g.dims[0] > g.dims[1] ? (g.dims[0] > g.dims[2] ? g.dims[0] : g.dims[2])
-                                        : (g.dims[1] > g.dims[2] ? g.dims[1] : g.dims[2]);
-    return ldexpf((float)m + 1.0f, -18);
-}
-
-// The Pre32 of slot k: its FP32 copy when PRE, an unused value otherwise.
+// The PreQ of slot k: its quantised copy when PRE, an unused value otherwise.
 template <bool PRE>
-__device__ __forceinline__ Pre32 pre32_of(const F4* __restrict__ pay32, int64_t k, const SimGeom& g)
+__device__ __forceinline__ PreQ preq_of(const uint2* __restrict__ payq, int64_t k)
 {
-    Pre32 r;
-    r.pay32 = pay32;
-    r.pi = F4{0.0f, 0.0f, 0.0f, 0.0f};
-    r.tol = 0.0f;
+    PreQ r;
+    r.payq = payq;
+    r.axy = 0u;
+    r.azr = 0u;
     if constexpr (PRE) {
-        r.pi = pay32[k];
-        r.tol = pre32_tol(g);
+        const uint2 v = payq[k];
+        const int rq = -(int)(int16_t)(v.y >> 16);
+        r.axy = v.x;
+        r.azr = (v.y & 0xffffu) | ((uint32_t)(rq + kQuantMargin) << 16);
     }
     return r;
 }
 
+// |u_q|^2 < (rq_i + rq_j + kQuantMargin)^2 on the quantised words of a candidate.
+__device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
+{
+    const ushort2v dxy = __builtin_bit_cast(ushort2v, p.axy) - __builtin_bit_cast(ushort2v, q.x);
+    const ushort2v dzr = __builtin_bit_cast(ushort2v, p.azr) - __builtin_bit_cast(ushort2v, q.y);
+    const short2v sxy = __builtin_bit_cast(short2v, dxy);
+    const short2v szr = __builtin_bit_cast(short2v, dzr);   // (dz, R)
+    const short2v nzr = szr * (short2v){1, -1};              // (dz, -R)
+    int t = __builtin_amdgcn_sdot2(sxy, sxy, 0, false);
+    t = __builtin_amdgcn_sdot2(szr, nzr, t, false);
+    return t < 0;
+}
+
 // Visit the candidates of agent `pi` that may touch it, in canonical order,
-// calling on_pair(offset, payload) for each candidate that passes the cheap
-// test |u|^2 < (ri + rj)^2 (offset = byte offset of its payload, self_off
-// that of the agent itself).  The caller's on_pair must still check
-// delta > 0 and |u| > 0: it sees the agent itself, and the list is handed
-// over in groups of four padded with the agent's own entry.
+// calling on_pair(offset, payload) for each candidate that passes a cheap
+// test that keeps every pair in contact (the quantised test of plain builds,
+// a slightly widened |u| < ri + rj otherwise; offset = byte offset of its
+// payload, self_off that of the agent itself).  The caller's on_pair must
+// still check delta > 0 and |u| > 0: it sees the agent itself, and the list
+// is handed over in groups of four padded with the agent's own entry.
 //
 // Two phases keep the wavefront busy.  The scan walks the 9 trimmed runs;
 // four candidates are loaded before any is tested (offsets clamped into the
@@ -287,8 +308,8 @@ __device__ __forceinline__ Pre32 pre32_of(const F4* __restrict__ pay32, int64_t 
 // drained (by the whole wavefront at once) before a group of four could
 // overflow any lane's list, so pairs are handed over in candidate order.
 // Offsets are 32-bit: a workspace holds fewer than 2^32 payload bytes.
-// PRE: the scan tests the FP32 slot copy `pre` instead of the payload (FP64
-// plain builds); the list then holds copy offsets, scaled to payload offsets
+// PRE: the scan tests the quantised slot copy `pre` instead of the payload
+// (plain builds); the list then holds copy offsets, scaled to payload offsets
 // when drained.
 template <typename Real, typename Pay, int LIST = kMaxContacts, bool PRE = false, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
@@ -296,15 +317,14 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
                                               const int32_t* __restrict__ start,
                                               const uint32_t* __restrict__ split,
                                               const Pay* __restrict__ pay, uint32_t* lst,
-                                              const Pre32& pre, OnPair&& on_pair)
+                                              const PreQ& pre, OnPair&& on_pair)
 {
-    static_assert(!PRE || sizeof(Pay) == 2 * sizeof(F4), "the FP32 copy serves FP64 payloads");
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
-    constexpr uint32_t PS = PRE ? (uint32_t)sizeof(F4) : P;   // bytes per scanned candidate
-    constexpr uint32_t SH = PRE ? 1u : 0u;                      // scan offset -> payload offset
+    constexpr uint32_t PS = PRE ? (uint32_t)sizeof(uint2) : P;   // bytes per scanned candidate
+    constexpr uint32_t SH = P == 32 ? 2u : 1u;                     // copy offset -> payload offset
     static_assert(LIST % 4 == 0, "the list drains in groups of four");
     const char* base = reinterpret_cast<const char*>(pay);
-    const char* sbase = PRE ? reinterpret_cast<const char*>(pre.pay32) : base;
+    const char* sbase = PRE ? reinterpret_cast<const char*>(pre.payq) : base;
     int cnt = 0;
     auto drain = [&]() {
         for (int t = 0; t < cnt; t += 4) {
@@ -313,7 +333,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t v = lst[(t + u) * kBlock];
-                o[u] = (t + u < cnt) ? (v << SH) : self_off;
+                o[u] = (t + u < cnt) ? (PRE ? (v << SH) : v) : self_off;
             }
             pin4(o);
 #pragma unroll
@@ -326,21 +346,37 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
     auto test = [&](auto q, uint32_t off, bool live) {
         pin(q);
         if constexpr (PRE) {
-            const float ux = pre.pi.x - q.x, uy = pre.pi.y - q.y, uz = pre.pi.z - q.z;
-            const float l2 = len2(ux, uy, uz);
-            const float rt = pre.pi.w + q.w + pre.tol;
             lst[cnt * kBlock] = off;
-            cnt += (int)(live & (l2 < rt * rt));
+            cnt += (int)(live & quant_hit(pre, q));
         } else {
+            // |u| < (r_i + r_j)(1 + 2^-20): wide enough that every pair the
+            // pair work finds in contact (delta > 0, with its own square
+            // root or reciprocal square root) passes, as with the quantised
+            // test, so both tests hand over the same contacts
             const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
             const Real l2 = len2(ux, uy, uz);
             const Real rs = pi.w + q.w;
+            const Real rt = fmad(rs, (Real)0x1p-20, rs);
             lst[cnt * kBlock] = off;
-            cnt += (int)(live & (l2 < rs * rs));
+            cnt += (int)(live & (l2 < rt * rt));
         }
     };
-    using SPay = typename std::conditional<PRE, F4, Pay>::type;
+    using SPay = typename std::conditional<PRE, uint2, Pay>::type;
     const Runs R = stencil_runs<Real>(g, c, start, split, pi.x, pi.y, pi.z, pi.w);
+    // one group of four candidates from `off` of a run ending at `end`.  The
+    // scanned region has three spare entries after the last agent, so the
+    // loads past a run's end stay inside it; those slots are masked out of
+    // the test.
+    auto group = [&](uint32_t off, uint32_t end) {
+        const SPay q0 = *reinterpret_cast<const SPay*>(sbase + off);
+        const SPay q1 = *reinterpret_cast<const SPay*>(sbase + off + PS);
+        const SPay q2 = *reinterpret_cast<const SPay*>(sbase + off + 2 * PS);
+        const SPay q3 = *reinterpret_cast<const SPay*>(sbase + off + 3 * PS);
+        test(q0, off, true);
+        test(q1, off + PS, off + PS < end);
+        test(q2, off + 2 * PS, off + 2 * PS < end);
+        test(q3, off + 3 * PS, off + 3 * PS < end);
+    };
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
         const uint32_t end = (uint32_t)R.e[r] * PS;
@@ -348,17 +384,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
             // the whole wave drains when any lane's list is nearly full: the
             // lanes' drains run side by side instead of one after another
             if (__any(cnt > LIST - 4)) drain();
-            // The scanned region has three spare entries after the last
-            // agent, so the loads past a run's end stay inside it; those
-            // slots are masked out of the test.
-            const SPay q0 = *reinterpret_cast<const SPay*>(sbase + off);
-            const SPay q1 = *reinterpret_cast<const SPay*>(sbase + off + PS);
-            const SPay q2 = *reinterpret_cast<const SPay*>(sbase + off + 2 * PS);
-            const SPay q3 = *reinterpret_cast<const SPay*>(sbase + off + 3 * PS);
-            test(q0, off, true);
-            test(q1, off + PS, off + PS < end);
-            test(q2, off + 2 * PS, off + 2 * PS < end);
-            test(q3, off + 3 * PS, off + 3 * PS < end);
+            group(off, end);
         }
     }
     drain();
@@ -372,7 +398,7 @@ __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& p
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          uint32_t* lst, const Pre32& pre, Real& fx, Real& fy,
+                                          uint32_t* lst, const PreQ& pre, Real& fx, Real& fy,
                                           Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;

@@ -303,6 +303,8 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         hdr->nb = err ? 0 : (int32_t)nbk;
         hdr->total_rows = err ? 0 : (int32_t)rows;
         hdr->build_gen = hdr->build_gen + 1u;
+        hdr->gather = hdr->next_sorted;
+        hdr->next_sorted = 0u;
         if (!err) start[running] = (int32_t)n;
     }
 }
@@ -365,6 +367,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                     hdr->nb = err ? 0 : (int32_t)nb;
                     hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
                     hdr->build_gen = hdr->build_gen + 1u;
+                    hdr->gather = hdr->next_sorted;
+                    hdr->next_sorted = 0u;
                     if (!err) start[boxes] = (int32_t)n;
                 }
             }
@@ -433,6 +437,34 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(const Header* __restrict__ h
     if (threadIdx.x == 0) btot[b] = running;
 }
 
+// Where the bucket sort takes an agent's sorted payload (x, y, z, d/2) from:
+// the partition's copy, or (gather mode) the inputs at its input index.
+// Gather mode is taken when the previous call on the workspace wrote a state
+// in its slot order (the sorted-state step, or the reorder of the caller's
+// arrays): such input is nearly box-sorted, so the inputs of one bucket are
+// nearly contiguous, and the partition then skips reading and writing the
+// payload.  It is only a question of speed: both modes give the same build
+// for any input.
+template <int M>
+struct PaySrc {
+    using In = typename Mode<M>::In;
+    using Real = typename Mode<M>::Real;
+    using Pay = typename Mode<M>::Pay;
+    const Pay* pay2;
+    const In *x, *y, *z, *d;
+    bool gather;
+    __device__ __forceinline__ Pay get(int64_t pos, int64_t id) const
+    {
+        if (!gather) return pay2[pos];
+        Pay q;
+        q.x = (Real)x[id];
+        q.y = (Real)y[id];
+        q.z = (Real)z[id];
+        q.w = (Real)0.5 * (Real)d[id];
+        return q;
+    }
+};
+
 // ---------------------------------------------------------------- partition
 
 // Each block orders its tile by bucket in LDS, then writes every bucket's run
@@ -460,6 +492,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     __shared__ int32_t s_wave[kTileThreads / kWave];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
+    const bool gat = hdr->gather != 0u;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
     const unsigned tile = xcd_block();   // consecutive tiles on one XCD
@@ -504,7 +537,8 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
         if (e < tn) order[cnt[bk[t]] + rk[t]] = (uint16_t)e;
     }
     __syncthreads();
-    // gather inside the tile (all loads of a group issued before any store)
+    // gather inside the tile (all loads of a group issued before any store);
+    // in gather mode the bucket sort reads the payload from the inputs itself
     constexpr int G = 4;
     for (int p0 = threadIdx.x; p0 < tn; p0 += G * kTileThreads) {
         int64_t i[G];
@@ -519,10 +553,12 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
         for (int t = 0; t < G; ++t) {
             key[t] = box_id[i[t]];
             qx[t] = quarter[i[t]];
-            q[t].x = (Real)x[i[t]];
-            q[t].y = (Real)y[i[t]];
-            q[t].z = (Real)z[i[t]];
-            q[t].w = (Real)0.5 * (Real)d[i[t]];
+            if (!gat) {
+                q[t].x = (Real)x[i[t]];
+                q[t].y = (Real)y[i[t]];
+                q[t].z = (Real)z[i[t]];
+                q[t].w = (Real)0.5 * (Real)d[i[t]];
+            }
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
@@ -531,7 +567,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
                 const int pos = gcur[key[t] >> sb] + p;
                 key2[pos] = ((key[t] & ((1 << sb) - 1)) << 2) | qx[t];
                 idx2[pos] = (int32_t)i[t];
-                pay2[pos] = q[t];
+                if (!gat) pay2[pos] = q[t];
             }
         }
     }
@@ -567,6 +603,8 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
     __shared__ int32_t s_wave[kTileThreads / kWave];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
+    // in gather mode the bucket sort reads the payload from the inputs itself
+    const bool gat = hdr->gather != 0u;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
     const unsigned tile = xcd_block();   // consecutive tiles on one XCD
@@ -582,10 +620,12 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
             const int64_t i = c0 + e;
             key[t] = box_id[i];
             qx[t] = quarter[i];
-            q[t].x = (Real)x[i];
-            q[t].y = (Real)y[i];
-            q[t].z = (Real)z[i];
-            q[t].w = (Real)0.5 * (Real)d[i];
+            if (!gat) {
+                q[t].x = (Real)x[i];
+                q[t].y = (Real)y[i];
+                q[t].z = (Real)z[i];
+                q[t].w = (Real)0.5 * (Real)d[i];
+            }
         }
     }
 #pragma unroll
@@ -621,7 +661,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
             const int pos = cnt[key[t] >> sb] + rk[t];
             s_key[pos] = key[t];
             s_eq[pos] = (uint16_t)(e | (qx[t] << 12));
-            s_pay[pos] = q[t];
+            if (!gat) s_pay[pos] = q[t];
         }
     }
     __syncthreads();
@@ -632,7 +672,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
         const int pos = gcur[k >> sb] + p;
         key2[pos] = ((k & ((1 << sb) - 1)) << 2) | (eq >> 12);
         idx2[pos] = (int32_t)(c0 + (eq & 0xfff));
-        pay2[pos] = s_pay[p];
+        if (!gat) pay2[pos] = s_pay[p];
     }
 }
 
@@ -654,36 +694,36 @@ __device__ __forceinline__ uint32_t split_word(uint32_t w, int cnt)
     return cnt > 255 ? kSplitNone : (w | ((uint32_t)cnt << 24));
 }
 
-// FP32 copy of each FP64 slot for the gather's candidate test (plain FP64
-// builds): coordinates relative to the grid origin and the radius, both in
-// units of the box edge, so every value is bounded by the box count per axis
-// and nothing overflows.  `on` is false for the other builds.
-struct Slot32 {
-    F4* p;
-    double o0, o1, o2, ie;
+// Quantised copy of each slot for the gather's candidate test (plain builds;
+// the test and why it never rejects a contact are in gather.hpp): x, y, z
+// relative to the grid origin in units of e / kQuantScale rounded down, kept
+// modulo 2^16, and the radius in the same units rounded up and negated, as
+// ((x | y << 16), (z | -r << 16)).  The positions are the payload's (the
+// values the force uses).  `on` is false for batched builds.
+struct SlotQ {
+    uint2* p;
+    double o0, o1, o2, sc;
     bool on;
-    __device__ Slot32(F4* pay32, const SimGeom* g)
-        : p(pay32), o0(0.0), o1(0.0), o2(0.0), ie(0.0), on(g != nullptr)
+    __device__ SlotQ(uint2* payq, const SimGeom* g)
+        : p(payq), o0(0.0), o1(0.0), o2(0.0), sc(0.0), on(g != nullptr)
     {
         if (on) {
             o0 = g->origin[0];
             o1 = g->origin[1];
             o2 = g->origin[2];
-            ie = 1.0 / g->edge;
+            sc = (double)kQuantScale / g->edge;
         }
     }
+    __device__ static uint32_t q16(double v) { return (uint32_t)(int64_t)floor(v) & 0xffffu; }
     template <typename Pay>
     __device__ __forceinline__ void put(int slot, const Pay& q) const
     {
-        if constexpr (sizeof(Pay) == sizeof(D4)) {
-            if (on) {
-                F4 v;
-                v.x = (float)((q.x - o0) * ie);
-                v.y = (float)((q.y - o1) * ie);
-                v.z = (float)((q.z - o2) * ie);
-                v.w = (float)(q.w * ie);
-                p[slot] = v;
-            }
+        if (on) {
+            const uint32_t xq = q16(((double)q.x - o0) * sc);
+            const uint32_t yq = q16(((double)q.y - o1) * sc);
+            const uint32_t zq = q16(((double)q.z - o2) * sc);
+            const int rq = (int)ceil((double)q.w * sc);
+            p[slot] = make_uint2(xq | (yq << 16), zq | ((uint32_t)(-rq) << 16));
         }
     }
 };
@@ -700,10 +740,10 @@ template <int M>
 __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t* mem, uint8_t* memq,
                             int32_t* inv, const int32_t* __restrict__ key2,
                             const int32_t* __restrict__ idx2,
-                            const typename Mode<M>::Pay* __restrict__ pay2,
+                            const PaySrc<M>& src,
                             const int32_t* __restrict__ tmp, uint32_t* __restrict__ split,
                             int32_t* __restrict__ perm, typename Mode<M>::Pay* __restrict__ pay,
-                            const Slot32& s32)
+                            const SlotQ& s32)
 {
     int kb = 0, cs = 0;   // first box and first slot of the chunk (block-uniform)
     while (kb < nbox) {
@@ -772,7 +812,7 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
             }
             typename Mode<M>::Pay q[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) q[u] = pay2[s0 + pm[u]];
+            for (int u = 0; u < U; ++u) q[u] = src.get(s0 + pm[u], mem[jj[u]]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = threadIdx.x + u * kSortThreads;
@@ -799,7 +839,7 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 if (r == 0)
                     reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + cs), kSplitNone);
                 perm[s0 + cs + r] = orig;
-                const typename Mode<M>::Pay qv = pay2[s0 + pe];
+                const typename Mode<M>::Pay qv = src.get(s0 + pe, orig);
                 pay[s0 + cs + r] = qv;
                 s32.put(s0 + cs + r, qv);
             }
@@ -814,13 +854,17 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              const int32_t* __restrict__ key2,
                                                              const int32_t* __restrict__ idx2,
                                                              const typename Mode<M>::Pay* __restrict__ pay2,
+                                                             const typename Mode<M>::In* __restrict__ x,
+                                                             const typename Mode<M>::In* __restrict__ y,
+                                                             const typename Mode<M>::In* __restrict__ z,
+                                                             const typename Mode<M>::In* __restrict__ d,
                                                              const int32_t* __restrict__ btot,
                                                              int32_t* __restrict__ start,
                                                              uint32_t* __restrict__ split,
                                                              int32_t* __restrict__ tmp,
                                                              int32_t* __restrict__ perm,
                                                              typename Mode<M>::Pay* __restrict__ pay,
-                                                             F4* __restrict__ pay32,
+                                                             uint2* __restrict__ payq,
                                                              const SimGeom* __restrict__ g32)
 {
     __shared__ int32_t c[kSortBoxes];
@@ -846,6 +890,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     const int s1 = s0 + btot[b];
     const bool staged = (s1 - s0) <= kSortStage;   // block-uniform
+    const PaySrc<M> src{pay2, x, y, z, d, hdr->gather != 0u};
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
@@ -911,8 +956,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     }
     __syncthreads();
     if (!staged) {   // block-uniform
-        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, pay2, tmp, split, perm, pay,
-                       Slot32(pay32, g32));
+        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, src, tmp, split, perm, pay,
+                       SlotQ(payq, g32));
         return;
     }
     // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
@@ -938,7 +983,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     // 5. write the sorted bucket in slot order (loads issued before the stores)
     if (s1 > s0) {   // block-uniform; padding lanes read slot s0
-        const Slot32 s32(pay32, g32);
+        const SlotQ s32(payq, g32);
         constexpr int U = kSortStage / kSortThreads;
         const int cnt = s1 - s0;
         int e[U];
@@ -950,10 +995,9 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
         int32_t id[U];
         typename Mode<M>::Pay q[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            id[u] = idx2[e[u]];
-            q[u] = pay2[e[u]];
-        }
+        for (int u = 0; u < U; ++u) id[u] = idx2[e[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = src.get(e[u], id[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = threadIdx.x + u * kSortThreads;
@@ -1036,10 +1080,11 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
                                                     D.hist, btot, D.key2, D.idx2,
                                                     static_cast<Pay*>(D.pay2));
     k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
-        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), btot, D.start, D.split, D.tmp,
+        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
+        D.split, D.tmp,
         D.perm,
-        static_cast<Pay*>(D.payload), D.pay32,
-        (M == MS_F64 && !batched) ? static_cast<const SimGeom*>(D.geom) : nullptr);
+        static_cast<Pay*>(D.payload), D.payq,
+        batched ? nullptr : static_cast<const SimGeom*>(D.geom));
     return hipGetLastError();
 }
 

@@ -80,6 +80,7 @@ def test_sorted_state_fixed_point_and_parity(case, mode):
     ts = [ms.reorder(ws, a) for a in t]
     ms.grid_build(ws, *ts)
     assert np.array_equal(slot_order(ws, n), np.arange(n))
+    _check_grid(ws, [a.cpu().numpy() for a in ts], mode)
     D = ms.mech_step(ws, P)
     ms.device_status(ws)
     sorted_arrs = [a.cpu().numpy() for a in ts]
@@ -89,6 +90,47 @@ def test_sorted_state_fixed_point_and_parity(case, mode):
     Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
     bound = P["dt"] * force_bound(S, A, mode) + 8 * UNIT[mode] * np.linalg.norm(Do, axis=1)
     check_vectors(Dg, Do, bound, f"sorted state {case} {mode}")
+
+
+def _check_grid(ws, arrs, mode):
+    """Geometry, box ids, box starts and the canonical order of the last build
+    equal the oracle's grid of the same inputs."""
+    g = ms.grid_get(ws)
+    o = oracle_inputs(arrs, mode)
+    origin, edge, dims, nb = oracle.geometry(*o)
+    box, start, perm = oracle.grid(*o)
+    info = g["info"][0]
+    assert info["edge"] == edge and info["n_boxes"] == nb
+    assert tuple(info["dims"]) == tuple(int(v) for v in dims)
+    assert np.array_equal(np.array(info["origin"]), origin)
+    assert np.array_equal(g["box_id"].cpu().numpy(), box)
+    assert np.array_equal(g["start"].cpu().numpy(), start)
+    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+
+
+@pytest.mark.parametrize("mode", ["f32", "f64"])
+def test_sorted_input_grid_2M(mode):
+    """2,097,152 agents: the build from the random input order moves the
+    payload through its partition, the build after a sorted-state step (the
+    state one step of motion later, as in a rollout) reads it from the
+    inputs; both grids equal the oracle's exactly."""
+    arrs = workloads.uniform(workloads.FULL_N, mean_neighbors=12.0, seed=5).arrays()
+    n = len(arrs[0])
+    ws = ms.Workspace(n, dtype=mode)
+    t = dev(arrs, mode)
+    ms.grid_build(ws, *t)
+    _check_grid(ws, arrs, mode)
+    so = ms.mech_step_integrate_sorted(ws, P, *t)
+    ms.device_status(ws)
+    moved = [a.cpu().numpy() for a in so]
+    ms.grid_build(ws, *so)
+    _check_grid(ws, moved, mode)
+    # the mode of a build is only a question of speed: after another sorted
+    # step, a build from the random order (payload read from the inputs)
+    # still equals the oracle's grid
+    ms.mech_step_integrate_sorted(ws, P, *so)
+    ms.grid_build(ws, *t)
+    _check_grid(ws, arrs, mode)
 
 
 def test_sorted_rollout_matches_plain_rollout():
