@@ -656,8 +656,18 @@ def main():
     fb = force_bytes(N, st["n_boxes"], S, sorted_head)
     prof = f"{name}_{args.dtype}" + ("_sorted" if sorted_head else "")
     issue = issue_from_profiles(prof)
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
-                    frac=achieved / peak, traffic=traffic_from_profiles(prof),
+    traffic = traffic_from_profiles(prof)
+    # Which roof binds, from the committed counters of the current sources:
+    # the share of the SIMD cycles the kernel spends issuing VALU
+    # instructions against the share of the HBM peak its counted traffic
+    # uses over the measured launch.  Without counters the bound stays the
+    # arithmetic one the flop count is priced against.
+    hbm_use = traffic / (force_ms * 1e-3) / HBM_PEAK if traffic else None
+    bound = "alu"
+    if issue and hbm_use is not None and hbm_use > issue["valu_issue_frac"]:
+        bound = "hbm"
+    roofline = dict(bound=bound, achieved=achieved / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=traffic, traffic_hbm_frac=hbm_use,
                     kernel=("k_force (ms_mech_step_integrate_sorted: gather, Eq. 1, displacement "
                             "and the state after the step in slot order)") if sorted_head else
                     "ms_mech_step = k_force + k_soa", flops_per_agent=flops_agent,
@@ -665,8 +675,11 @@ def main():
                     force_alg_bytes=fb, force_alg_GBps=fb / (force_ms * 1e-3) / 1e9,
                     force_hbm_frac=fb / (force_ms * 1e-3) / HBM_PEAK,
                     issue=issue,
-                    bound_evidence=("VALU issue and texture units busy (rocprofv3 counters); the "
-                                    "force step's algorithmic bytes move at force_hbm_frac of HBM")
+                    bound_evidence=(f"VALU issue {issue['valu_issue_frac']:.2f} of the SIMD cycles, "
+                                    f"texture data unit busy {issue['td_busy_frac']:.2f} (rocprofv3 "
+                                    "counters) against counted HBM traffic at "
+                                    + (f"{hbm_use:.2f}" if hbm_use is not None else "an unmeasured share")
+                                    + " of the HBM peak")
                     if issue else None)
     balg = bytes_alg(N, st["n_boxes"], S)
     hbm = dict(step_alg_bytes=balg, step_alg_GBps=balg * args.steps / sec / 1e9,

@@ -104,7 +104,8 @@ typedef struct {
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
  * fields from n_agents to built are updated by the grid builds.  Treat them as
- * read-only; keep_forces and gather_list are the caller's to set. */
+ * read-only; keep_forces, gather_list and sorted_input are the caller's to
+ * set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -128,6 +129,15 @@ typedef struct {
                             populations; shorter ones leave LDS for more blocks
                             per CU.  Results are identical bit for bit; the
                             package's autotuner picks the faster one. */
+    int32_t sorted_input; /* 1: the next build's inputs are nearly box-sorted
+                            (set by ms_mech_step_integrate_sorted, the batched
+                            variant and ms_reorder, which write arrays in the
+                            build's slot order; cleared by every build).  Such
+                            a build reads each agent's position and diameter
+                            from its inputs instead of carrying them through
+                            its partition.  Only the speed depends on it: the
+                            build is the same for any input, and the caller
+                            may set or clear it. */
 } ms_workspace;
 
 /* Bytes of device memory a workspace with these capacities needs (0 for
@@ -230,10 +240,8 @@ ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_para
  * state after the step is written to new arrays in the slot order of the
  * build (agent perm[k] at k, the order ms_reorder applies: ascending box,
  * x-quarter inside the box, input index), so every store of the step is
- * coalesced and the next build reads nearly sorted input.  The next build on
- * the same workspace then takes each agent's position and diameter straight
- * from its inputs instead of carrying them through its partition (faster on
- * nearly sorted input; the build is the same for any input).
+ * coalesced and the next build reads nearly sorted input (the call sets
+ * ws->sorted_input).
  *   x_out, y_out, z_out [n]  positions after the step (p + Delta, rounded as
  *                            ms_mech_step_integrate rounds them), slot order
  *   d_out [n]                the diameters, slot order (for MS_F32 and MS_F64
@@ -252,14 +260,14 @@ ms_status ms_mech_step_backward_accumulate(const ms_workspace* ws, const ms_para
  * rollout to rounding, step by step within the same acceptance bound.  On a
  * device error of the build nothing is written.
  * Stream-ordered; allocates nothing. */
-ms_status ms_mech_step_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+ms_status ms_mech_step_integrate_sorted(ms_workspace* ws, const ms_params* params,
                                         const void* x, const void* y, const void* z, const void* d,
                                         void* x_out, void* y_out, void* z_out, void* d_out,
                                         void* dx, void* dy, void* dz, void* stream);
 
 /* The same for every simulation of the last batched build (params: device
  * ms_params [B]); agents of each simulation stay in its offset range. */
-ms_status ms_mech_step_batched_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+ms_status ms_mech_step_batched_integrate_sorted(ms_workspace* ws, const ms_params* params,
                                                 const void* x, const void* y, const void* z,
                                                 const void* d, void* x_out, void* y_out,
                                                 void* z_out, void* d_out, void* dx, void* dy,
@@ -290,15 +298,14 @@ ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy
  * canonical order, ascending box then input index; both are box-sorted.)
  * Applying it to every per-agent array of the caller (positions, diameters and
  * any attributes) renumbers the agents in box order, so the next build reads
- * nearly sorted input and writes the displacements nearly in order (and, as
- * after ms_mech_step_integrate_sorted, takes the payload from its inputs);
- * agents of one simulation of a batched build stay inside that simulation's
- * range.
+ * nearly sorted input and writes the displacements nearly in order (the call
+ * sets ws->sorted_input); agents of one simulation of a batched build stay
+ * inside that simulation's range.
  * src, dst: device arrays of n_agents elements of elem_bytes (1, 2, 4, 8 or
  * 16) bytes, aligned to elem_bytes; they must not overlap (MS_EINVAL).  The
  * caller owns both.  A device error of the last build leaves dst unwritten.
  * Stream-ordered; allocates nothing. */
-ms_status ms_reorder(const ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
+ms_status ms_reorder(ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
                      void* stream);
 
 /* Copy out the last build (synchronises `stream`).  info: host array with

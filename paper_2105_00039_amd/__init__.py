@@ -103,6 +103,16 @@ class Workspace:
         self.c.gather_list = int(v)
 
     @property
+    def sorted_input(self) -> bool:
+        """Whether the next build takes its inputs as nearly box-sorted (set by
+        the sorted-state step and reorder, cleared by every build; speed only)."""
+        return bool(self.c.sorted_input)
+
+    @sorted_input.setter
+    def sorted_input(self, on: bool):
+        self.c.sorted_input = 1 if on else 0
+
+    @property
     def keep_forces(self) -> bool:
         """Whether mech_step keeps the forces for the next mech_step_backward
         on the same build and parameters (which then skips recomputing them)."""

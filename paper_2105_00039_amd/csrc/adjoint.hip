@@ -52,7 +52,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    constexpr bool PRE = !BATCHED;   // plain builds scan their quantised slot copy
     __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
@@ -69,9 +68,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
         const Pay f = fsave[k];
         fx = f.x; fy = f.y; fz = f.z;
     } else {
-        force_sum<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
+        force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                         pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                                        preq_of<PRE>(payq, k), fx, fy, fz);
+                                        preq_of(payq, k), fx, fy, fz);
     }
     const Pay gr = gin[perm[k]];
     const Real gx = gr.x, gy = gr.y, gz = gr.z;
@@ -175,7 +174,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
-    constexpr bool PRE = !BATCHED;   // plain builds scan their quantised slot copy
     __shared__ double s_w[kBlock / kWave];
     __shared__ int s_rng[2];
     __shared__ uint32_t lst[LIST * kBlock];
@@ -203,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
         const char* fbase = reinterpret_cast<const char*>(fbar);
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
-        scan_contacts<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start,
+        scan_contacts<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start,
                                             split, pay, lst + threadIdx.x,
-                                            preq_of<PRE>(payq, k),
+                                            preq_of(payq, k),
                                             [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
             Pay fj = *reinterpret_cast<const Pay*>(fbase + off);

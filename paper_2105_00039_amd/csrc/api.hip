@@ -117,6 +117,7 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->built = 0;
     ws->keep_forces = 0;
     ws->gather_list = 0;
+    ws->sorted_input = 0;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -141,10 +142,12 @@ static ms_status build_common(ms_workspace* ws, const void* x, const void* y, co
     ws->n_agents = n;
     ws->n_sims = B;
     ws->built = off ? 2 : 1;
+    const bool sorted_input = ws->sorted_input != 0;
+    ws->sorted_input = 0;
     if (n == 0) return ok();
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_grid_build(L, ms::resolve(L, ws->base), x, y, z, d, n, off, B, edge,
-                                           edges, as_stream(stream)),
+                                           edges, sorted_input, as_stream(stream)),
                      who);
 }
 
@@ -233,7 +236,7 @@ ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, voi
 
 // The sorted-state step: arguments checked, then the force kernel writes the
 // state after the step in slot order.
-static ms_status step_sorted_common(const ms_workspace* ws, bool batched, const ms_params* p,
+static ms_status step_sorted_common(ms_workspace* ws, bool batched, const ms_params* p,
                                     const void* x, const void* y, const void* z, const void* d,
                                     void* xo, void* yo, void* zo, void* dout, void* dx, void* dy,
                                     void* dz, void* stream, const char* who)
@@ -265,6 +268,7 @@ static ms_status step_sorted_common(const ms_workspace* ws, bool batched, const 
             if (u < v + len && v < u + len) return fail(MS_EINVAL, "%s: output arrays overlap", who);
         }
     ms::SortedState so{xo, yo, zo, dout, x, y, z, d};
+    ws->sorted_input = 1;   // the state written in slot order feeds the next build
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
                                       batched, batched ? nullptr : p, batched ? p : nullptr, dx, dy,
@@ -274,7 +278,7 @@ static ms_status step_sorted_common(const ms_workspace* ws, bool batched, const 
                      who);
 }
 
-ms_status ms_mech_step_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+ms_status ms_mech_step_integrate_sorted(ms_workspace* ws, const ms_params* params,
                                         const void* x, const void* y, const void* z, const void* d,
                                         void* x_out, void* y_out, void* z_out, void* d_out,
                                         void* dx, void* dy, void* dz, void* stream)
@@ -283,7 +287,7 @@ ms_status ms_mech_step_integrate_sorted(const ms_workspace* ws, const ms_params*
                               stream, "ms_mech_step_integrate_sorted");
 }
 
-ms_status ms_mech_step_batched_integrate_sorted(const ms_workspace* ws, const ms_params* params,
+ms_status ms_mech_step_batched_integrate_sorted(ms_workspace* ws, const ms_params* params,
                                                 const void* x, const void* y, const void* z,
                                                 const void* d, void* x_out, void* y_out,
                                                 void* z_out, void* d_out, void* dx, void* dy,
@@ -402,7 +406,7 @@ ms_status ms_integrate(void* x, void* y, void* z, const void* dx, const void* dy
     return check_hip(ms::launch_integrate(x, y, z, dx, dy, dz, n, dtype, as_stream(stream)), who);
 }
 
-ms_status ms_reorder(const ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
+ms_status ms_reorder(ms_workspace* ws, const void* src, void* dst, int32_t elem_bytes,
                      void* stream)
 {
     const char* who = "ms_reorder";
@@ -417,6 +421,7 @@ ms_status ms_reorder(const ms_workspace* ws, const void* src, void* dst, int32_t
     const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
     const uintptr_t len = (uintptr_t)n * (uintptr_t)elem_bytes;
     if (a < b + len && b < a + len) return fail(MS_EINVAL, "%s: src and dst overlap", who);
+    ws->sorted_input = 1;   // arrays renumbered into slot order feed the next build
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_reorder(ms::resolve(L, ws->base), n, src, dst, elem_bytes,
                                         as_stream(stream)),
@@ -619,7 +624,7 @@ ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, cons
     // a fresh header for every call: the array keeps the previous call's state
     hipError_t e = ms::launch_init(L, D, s);
     if (e == hipSuccess && n > 0)
-        e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, s);
+        e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, false, s);
     if (e == hipSuccess && n > 0)
         e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
                              false, ms::kMaxContacts, s);

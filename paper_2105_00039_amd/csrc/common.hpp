@@ -57,9 +57,7 @@ struct Header {
     uint32_t build_gen;    // incremented by every build
     uint32_t fwd_gen;      // build_gen of the forward step that kept its forces
     ms_params fwd_params;  // parameters of that forward step
-    uint32_t gather;       // 1: the current build's partition moves keys and indices only
-    uint32_t next_sorted;  // 1: the last call wrote a state in slot order (sorted step, reorder)
-    uint8_t pad[256 - 104];
+    uint8_t pad[256 - 96];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -139,8 +137,8 @@ constexpr Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_
     L.perm = take(4 * (size_t)na);
     // three extra entries: the gather reads up to three slots past a run's end
     L.payload = take(pay * (size_t)(na + 3));
-    // builds of one simulation: an 8-byte quantised copy of each slot for the
-    // gather's candidate test (same three extra entries)
+    // an 8-byte quantised copy of each slot for the gather's candidate test
+    // (same three extra entries)
     L.payq = take(8 * (size_t)(na + 3));
     L.fbar = take(pay * (size_t)na);
     L.fsave = take(pay * (size_t)na);
@@ -174,7 +172,7 @@ struct Dev {
     int32_t* canon;
     int32_t* cslot;
     void* payload;
-    uint2* payq;        // plain builds: quantised (x, y | z, -r) of each slot (gather.hpp)
+    uint2* payq;        // quantised (x, y | z, -r) of each slot (gather.hpp)
     void* fbar;
     void* fsave;        // forces of the last forward step that kept them (slot order)
     double* partials;

@@ -52,8 +52,6 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     using Real = typename Mode<M>::Real;
     using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
-    // plain builds scan their quantised slot copy
-    constexpr bool PRE = !BATCHED;
     __shared__ uint32_t lst[LIST * kBlock];
     if (hdr->error) return;
     // forces kept for the backward step: record which build and parameters
@@ -62,9 +60,6 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
         hdr->fwd_gen = hdr->build_gen;
         hdr->fwd_params = p1;
     }
-    // the state written in slot order is nearly box-sorted for the next build
-    // (which then moves only keys and indices through its partition)
-    if (SORTED && blockIdx.x == 0 && threadIdx.x == 0) hdr->next_sorted = 1u;
     const int64_t k0 = (int64_t)xcd_block() * kBlock;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
@@ -75,9 +70,9 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay, LIST, PRE>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
+    force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                     pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                                    preq_of<PRE>(payq, k), fx, fy, fz);
+                                    preq_of(payq, k), fx, fy, fz);
     if (fsave) {
         Pay f;
         f.x = fx; f.y = fy; f.z = fz; f.w = (Real)0;
@@ -429,11 +424,9 @@ hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reorder(const int32_t* __restrict__ perm,
                                                     const T* __restrict__ src, T* __restrict__ dst,
-                                                    int64_t n, Header* __restrict__ hdr)
+                                                    int64_t n, const Header* __restrict__ hdr)
 {
     if (hdr->error) return;
-    // arrays renumbered into slot order make the next build's input box-sorted
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next_sorted = 1u;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k < n) dst[k] = src[perm[k]];
 }

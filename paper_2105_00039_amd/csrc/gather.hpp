@@ -237,7 +237,7 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     return R;
 }
 
-// Candidate test of plain builds on the quantised slot copy the build writes
+// Candidate test on the quantised slot copy the build writes
 // (one 8-byte word pair per slot): x, y, z relative to the grid origin in
 // units of e / kQuantScale, rounded down, each kept modulo 2^16, and the
 // radius in the same units rounded up, stored negated.  A stencil candidate
@@ -261,20 +261,15 @@ struct PreQ {
     uint32_t azr;   // its z quanta and rq + kQuantMargin
 };
 
-// The PreQ of slot k: its quantised copy when PRE, an unused value otherwise.
-template <bool PRE>
+// The PreQ of slot k: the agent's own quantised words.
 __device__ __forceinline__ PreQ preq_of(const uint2* __restrict__ payq, int64_t k)
 {
+    const uint2 v = payq[k];
+    const int rq = -(int)(int16_t)(v.y >> 16);
     PreQ r;
     r.payq = payq;
-    r.axy = 0u;
-    r.azr = 0u;
-    if constexpr (PRE) {
-        const uint2 v = payq[k];
-        const int rq = -(int)(int16_t)(v.y >> 16);
-        r.axy = v.x;
-        r.azr = (v.y & 0xffffu) | ((uint32_t)(rq + kQuantMargin) << 16);
-    }
+    r.axy = v.x;
+    r.azr = (v.y & 0xffffu) | ((uint32_t)(rq + kQuantMargin) << 16);
     return r;
 }
 
@@ -292,10 +287,9 @@ __device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
 }
 
 // Visit the candidates of agent `pi` that may touch it, in canonical order,
-// calling on_pair(offset, payload) for each candidate that passes a cheap
-// test that keeps every pair in contact (the quantised test of plain builds,
-// a slightly widened |u| < ri + rj otherwise; offset = byte offset of its
-// payload, self_off that of the agent itself).  The caller's on_pair must
+// calling on_pair(offset, payload) for each candidate that passes the
+// quantised test, which keeps every pair in contact (offset = byte offset of
+// its payload, self_off that of the agent itself).  The caller's on_pair must
 // still check delta > 0 and |u| > 0: it sees the agent itself, and the list
 // is handed over in groups of four padded with the agent's own entry.
 //
@@ -308,10 +302,9 @@ __device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
 // drained (by the whole wavefront at once) before a group of four could
 // overflow any lane's list, so pairs are handed over in candidate order.
 // Offsets are 32-bit: a workspace holds fewer than 2^32 payload bytes.
-// PRE: the scan tests the quantised slot copy `pre` instead of the payload
-// (plain builds); the list then holds copy offsets, scaled to payload offsets
-// when drained.
-template <typename Real, typename Pay, int LIST = kMaxContacts, bool PRE = false, typename OnPair>
+// The scan reads the quantised slot copy `pre`; the list holds copy offsets,
+// scaled to payload offsets when drained.
+template <typename Real, typename Pay, int LIST = kMaxContacts, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
@@ -320,11 +313,11 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
                                               const PreQ& pre, OnPair&& on_pair)
 {
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
-    constexpr uint32_t PS = PRE ? (uint32_t)sizeof(uint2) : P;   // bytes per scanned candidate
-    constexpr uint32_t SH = P == 32 ? 2u : 1u;                     // copy offset -> payload offset
+    constexpr uint32_t PS = (uint32_t)sizeof(uint2);   // bytes per scanned candidate
+    constexpr uint32_t SH = P == 32 ? 2u : 1u;         // copy offset -> payload offset
     static_assert(LIST % 4 == 0, "the list drains in groups of four");
     const char* base = reinterpret_cast<const char*>(pay);
-    const char* sbase = PRE ? reinterpret_cast<const char*>(pre.payq) : base;
+    const char* sbase = reinterpret_cast<const char*>(pre.payq);
     int cnt = 0;
     auto drain = [&]() {
         for (int t = 0; t < cnt; t += 4) {
@@ -333,7 +326,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t v = lst[(t + u) * kBlock];
-                o[u] = (t + u < cnt) ? (PRE ? (v << SH) : v) : self_off;
+                o[u] = (t + u < cnt) ? (v << SH) : self_off;
             }
             pin4(o);
 #pragma unroll
@@ -343,25 +336,12 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
         }
         cnt = 0;
     };
-    auto test = [&](auto q, uint32_t off, bool live) {
+    auto test = [&](uint2 q, uint32_t off, bool live) {
         pin(q);
-        if constexpr (PRE) {
-            lst[cnt * kBlock] = off;
-            cnt += (int)(live & quant_hit(pre, q));
-        } else {
-            // |u| < (r_i + r_j)(1 + 2^-20): wide enough that every pair the
-            // pair work finds in contact (delta > 0, with its own square
-            // root or reciprocal square root) passes, as with the quantised
-            // test, so both tests hand over the same contacts
-            const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
-            const Real l2 = len2(ux, uy, uz);
-            const Real rs = pi.w + q.w;
-            const Real rt = fmad(rs, (Real)0x1p-20, rs);
-            lst[cnt * kBlock] = off;
-            cnt += (int)(live & (l2 < rt * rt));
-        }
+        lst[cnt * kBlock] = off;
+        cnt += (int)(live & quant_hit(pre, q));
     };
-    using SPay = typename std::conditional<PRE, uint2, Pay>::type;
+    using SPay = uint2;
     const Runs R = stencil_runs<Real>(g, c, start, split, pi.x, pi.y, pi.z, pi.w);
     // one group of four candidates from `off` of a run ending at `end`.  The
     // scanned region has three spare entries after the last agent, so the
@@ -393,7 +373,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
 // order (contact_force drops non-overlapping pairs and the agent itself).
 // LIST: length of the per-lane contact list `lst` (stride kBlock).
-template <typename Real, typename Pay, int LIST = kMaxContacts, bool PRE = false>
+template <typename Real, typename Pay, int LIST = kMaxContacts>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
@@ -402,7 +382,7 @@ __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& p
                                           Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay, LIST, PRE>(g, c, pi, self_off, start, split, pay, lst, pre,
+    scan_contacts<Real, Pay, LIST>(g, c, pi, self_off, start, split, pay, lst, pre,
                                         [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });

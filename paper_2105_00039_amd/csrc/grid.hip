@@ -303,8 +303,6 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         hdr->nb = err ? 0 : (int32_t)nbk;
         hdr->total_rows = err ? 0 : (int32_t)rows;
         hdr->build_gen = hdr->build_gen + 1u;
-        hdr->gather = hdr->next_sorted;
-        hdr->next_sorted = 0u;
         if (!err) start[running] = (int32_t)n;
     }
 }
@@ -367,8 +365,6 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                     hdr->nb = err ? 0 : (int32_t)nb;
                     hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
                     hdr->build_gen = hdr->build_gen + 1u;
-                    hdr->gather = hdr->next_sorted;
-                    hdr->next_sorted = 0u;
                     if (!err) start[boxes] = (int32_t)n;
                 }
             }
@@ -438,24 +434,22 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(const Header* __restrict__ h
 }
 
 // Where the bucket sort takes an agent's sorted payload (x, y, z, d/2) from:
-// the partition's copy, or (gather mode) the inputs at its input index.
-// Gather mode is taken when the previous call on the workspace wrote a state
-// in its slot order (the sorted-state step, or the reorder of the caller's
-// arrays): such input is nearly box-sorted, so the inputs of one bucket are
-// nearly contiguous, and the partition then skips reading and writing the
-// payload.  It is only a question of speed: both modes give the same build
-// for any input.
-template <int M>
+// the partition's copy, or (GATHER) the inputs at its input index.  Builds
+// whose inputs are nearly box-sorted (the workspace's sorted_input switch:
+// the state a sorted-state step or a reorder wrote) take GATHER: the inputs
+// of one bucket are then nearly contiguous, and the partition skips reading
+// and writing the payload.  It is only a question of speed: both give the
+// same build for any input.
+template <int M, bool GATHER>
 struct PaySrc {
     using In = typename Mode<M>::In;
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
     const Pay* pay2;
     const In *x, *y, *z, *d;
-    bool gather;
     __device__ __forceinline__ Pay get(int64_t pos, int64_t id) const
     {
-        if (!gather) return pay2[pos];
+        if constexpr (!GATHER) return pay2[pos];
         Pay q;
         q.x = (Real)x[id];
         q.y = (Real)y[id];
@@ -470,7 +464,7 @@ struct PaySrc {
 // Each block orders its tile by bucket in LDS, then writes every bucket's run
 // contiguously (consecutive lanes -> consecutive addresses), reading the
 // agents' inputs inside the tile.
-template <int M>
+template <int M, bool GATHER>
 __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<M>::In* __restrict__ x,
                                                       const typename Mode<M>::In* __restrict__ y,
                                                       const typename Mode<M>::In* __restrict__ z,
@@ -492,7 +486,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
     __shared__ int32_t s_wave[kTileThreads / kWave];
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
-    const bool gat = hdr->gather != 0u;
+    constexpr bool gat = GATHER;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
     const unsigned tile = xcd_block();   // consecutive tiles on one XCD
@@ -577,7 +571,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(const typename Mode<
 // thread loads its own agents (coalesced), they are placed in bucket order in
 // LDS (key, tile position + quarter, payload), and each bucket run is then
 // written from LDS in order.  One block per CU (the tile needs ~120 KB).
-template <int M>
+template <int M, bool GATHER>
 __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename Mode<M>::In* __restrict__ x,
                                                                 const typename Mode<M>::In* __restrict__ y,
                                                                 const typename Mode<M>::In* __restrict__ z,
@@ -604,7 +598,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
     if (hdr->error) return;
     const int sb = hdr->sb, nbk = hdr->nb;
     // in gather mode the bucket sort reads the payload from the inputs itself
-    const bool gat = hdr->gather != 0u;
+    constexpr bool gat = GATHER;
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) cnt[b] = 0;
     __syncthreads();
     const unsigned tile = xcd_block();   // consecutive tiles on one XCD
@@ -694,39 +688,50 @@ __device__ __forceinline__ uint32_t split_word(uint32_t w, int cnt)
     return cnt > 255 ? kSplitNone : (w | ((uint32_t)cnt << 24));
 }
 
-// Quantised copy of each slot for the gather's candidate test (plain builds;
-// the test and why it never rejects a contact are in gather.hpp): x, y, z
-// relative to the grid origin in units of e / kQuantScale rounded down, kept
+// Quantised copy of each slot for the gather's candidate test (the test and
+// why it never rejects a contact are in gather.hpp): x, y, z relative to the
+// simulation's grid origin in units of e / kQuantScale rounded down, kept
 // modulo 2^16, and the radius in the same units rounded up and negated, as
 // ((x | y << 16), (z | -r << 16)).  The positions are the payload's (the
-// values the force uses).  `on` is false for batched builds.
+// values the force uses).  A batched build quantises each slot in its own
+// simulation's frame (agents of different simulations never meet); the
+// simulations of a bucket's boxes are found once per bucket.
 struct SlotQ {
     uint2* p;
-    double o0, o1, o2, sc;
-    bool on;
-    __device__ SlotQ(uint2* payq, const SimGeom* g)
-        : p(payq), o0(0.0), o1(0.0), o2(0.0), sc(0.0), on(g != nullptr)
-    {
-        if (on) {
-            o0 = g->origin[0];
-            o1 = g->origin[1];
-            o2 = g->origin[2];
-            sc = (double)kQuantScale / g->edge;
-        }
-    }
+    const SimGeom* g;
+    int slo, shi;   // simulations holding the bucket's first and last box
+    __device__ SlotQ(uint2* payq, const SimGeom* geom, int s_lo, int s_hi)
+        : p(payq), g(geom), slo(s_lo), shi(s_hi) {}
     __device__ static uint32_t q16(double v) { return (uint32_t)(int64_t)floor(v) & 0xffffu; }
+    // gbox: global box of the slot's agent
     template <typename Pay>
-    __device__ __forceinline__ void put(int slot, const Pay& q) const
+    __device__ __forceinline__ void put(int slot, const Pay& q, int gbox) const
     {
-        if (on) {
-            const uint32_t xq = q16(((double)q.x - o0) * sc);
-            const uint32_t yq = q16(((double)q.y - o1) * sc);
-            const uint32_t zq = q16(((double)q.z - o2) * sc);
-            const int rq = (int)ceil((double)q.w * sc);
-            p[slot] = make_uint2(xq | (yq << 16), zq | ((uint32_t)(-rq) << 16));
+        int lo = slo, hi = shi + 1;   // the last simulation with box_base <= gbox
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (g[mid].box_base <= gbox) lo = mid; else hi = mid;
         }
+        const SimGeom& f = g[lo];
+        const double sc = (double)kQuantScale / f.edge;
+        const uint32_t xq = q16(((double)q.x - f.origin[0]) * sc);
+        const uint32_t yq = q16(((double)q.y - f.origin[1]) * sc);
+        const uint32_t zq = q16(((double)q.z - f.origin[2]) * sc);
+        const int rq = (int)ceil((double)q.w * sc);
+        p[slot] = make_uint2(xq | (yq << 16), zq | ((uint32_t)(-rq) << 16));
     }
 };
+
+// Simulation of global box gbox among sims [0, B): the last with box_base <= gbox.
+__device__ __forceinline__ int sim_of_box(const SimGeom* __restrict__ g, int B, int gbox)
+{
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g[mid].box_base <= gbox) lo = mid; else hi = mid;
+    }
+    return lo;
+}
 
 // Buckets holding more agents than the LDS stage: after the box counts, box
 // starts and the arrival-order placement (tmp[s0 + slot] = position of the
@@ -736,11 +741,11 @@ struct SlotQ {
 // index) there, and written in slot order; a member's box is the one whose
 // slot range holds its arrival slot.  A single box above kSortStage agents is
 // ranked straight from global memory.
-template <int M>
+template <int M, bool GATHER>
 __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t* mem, uint8_t* memq,
                             int32_t* inv, const int32_t* __restrict__ key2,
                             const int32_t* __restrict__ idx2,
-                            const PaySrc<M>& src,
+                            const PaySrc<M, GATHER>& src,
                             const int32_t* __restrict__ tmp, uint32_t* __restrict__ split,
                             int32_t* __restrict__ perm, typename Mode<M>::Pay* __restrict__ pay,
                             const SlotQ& s32)
@@ -811,15 +816,19 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 pm[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
             }
             typename Mode<M>::Pay q[U];
+            int bx[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) q[u] = src.get(s0 + pm[u], mem[jj[u]]);
+            for (int u = 0; u < U; ++u) {
+                q[u] = src.get(s0 + pm[u], mem[jj[u]]);
+                bx[u] = b0 + (key2[s0 + pm[u]] >> 2);
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = threadIdx.x + u * kSortThreads;
                 if (p < cn) {
                     perm[s0 + cs + p] = mem[jj[u]];
                     pay[s0 + cs + p] = q[u];
-                    s32.put(s0 + cs + p, q[u]);
+                    s32.put(s0 + cs + p, q[u], bx[u]);
                 }
             }
             __syncthreads();
@@ -841,7 +850,7 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 perm[s0 + cs + r] = orig;
                 const typename Mode<M>::Pay qv = src.get(s0 + pe, orig);
                 pay[s0 + cs + r] = qv;
-                s32.put(s0 + cs + r, qv);
+                s32.put(s0 + cs + r, qv, b0 + k);
             }
         }
         kb = ke;
@@ -849,7 +858,7 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
     }
 }
 
-template <int M>
+template <int M, bool GATHER>
 __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __restrict__ hdr,
                                                              const int32_t* __restrict__ key2,
                                                              const int32_t* __restrict__ idx2,
@@ -865,9 +874,11 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
                                                              int32_t* __restrict__ perm,
                                                              typename Mode<M>::Pay* __restrict__ pay,
                                                              uint2* __restrict__ payq,
-                                                             const SimGeom* __restrict__ g32)
+                                                             const SimGeom* __restrict__ geom,
+                                                             int32_t B)
 {
     __shared__ int32_t c[kSortBoxes];
+    __shared__ int s_sims[2];
     __shared__ int32_t mem[kSortStage];      // input index of each box member, arrival order
     __shared__ uint8_t memq[kSortStage];     // its x-quarter
     __shared__ int32_t inv[kSortStage];      // final slot -> position in the bucket's input
@@ -890,7 +901,11 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     const int s1 = s0 + btot[b];
     const bool staged = (s1 - s0) <= kSortStage;   // block-uniform
-    const PaySrc<M> src{pay2, x, y, z, d, hdr->gather != 0u};
+    const PaySrc<M, GATHER> src{pay2, x, y, z, d};
+    if (threadIdx.x == 0) {
+        s_sims[0] = B > 1 ? sim_of_box(geom, B, b0) : 0;
+        s_sims[1] = B > 1 ? sim_of_box(geom, B, b0 + (nbox > 0 ? nbox - 1 : 0)) : 0;
+    }
     // 1. per-box counts
     for (int k = threadIdx.x; k < nbox; k += kSortThreads) c[k] = 0;
     __syncthreads();
@@ -956,8 +971,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     }
     __syncthreads();
     if (!staged) {   // block-uniform
-        sort_chunks<M>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, src, tmp, split, perm, pay,
-                       SlotQ(payq, g32));
+        sort_chunks<M, GATHER>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, src, tmp, split, perm, pay,
+                       SlotQ(payq, geom, s_sims[0], s_sims[1]));
         return;
     }
     // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
@@ -983,7 +998,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
     __syncthreads();
     // 5. write the sorted bucket in slot order (loads issued before the stores)
     if (s1 > s0) {   // block-uniform; padding lanes read slot s0
-        const SlotQ s32(payq, g32);
+        const SlotQ s32(payq, geom, s_sims[0], s_sims[1]);
         constexpr int U = kSortStage / kSortThreads;
         const int cnt = s1 - s0;
         int e[U];
@@ -992,10 +1007,13 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
             const int p = threadIdx.x + u * kSortThreads;
             e[u] = s0 + (p < cnt ? inv[p] : 0);
         }
-        int32_t id[U];
+        int32_t id[U], bx[U];
         typename Mode<M>::Pay q[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) id[u] = idx2[e[u]];
+        for (int u = 0; u < U; ++u) {
+            id[u] = idx2[e[u]];
+            bx[u] = b0 + (key2[e[u]] >> 2);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) q[u] = src.get(e[u], id[u]);
 #pragma unroll
@@ -1004,7 +1022,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucketsort(const Header* __res
             if (p < cnt) {
                 perm[s0 + p] = id[u];
                 pay[s0 + p] = q[u];
-                s32.put(s0 + p, q[u]);
+                s32.put(s0 + p, q[u], bx[u]);
             }
         }
     }
@@ -1034,10 +1052,34 @@ __global__ __launch_bounds__(kBlock) void k_canon(int64_t n, const Header* __res
     cslot[bs + r] = (int32_t)k;
 }
 
+// The partition and the per-bucket sort, payload carried (GATHER false) or
+// read from the inputs by the sort (GATHER true).
+template <int M, bool GATHER>
+void sort_passes(const Layout& L, const Dev& D, const typename Mode<M>::In* x,
+                 const typename Mode<M>::In* y, const typename Mode<M>::In* z,
+                 const typename Mode<M>::In* d, int64_t n, int32_t B, unsigned nba,
+                 const int32_t* btot, hipStream_t s)
+{
+    using Pay = typename Mode<M>::Pay;
+    if constexpr (sizeof(Pay) == sizeof(F4))
+        k_partition_lds<M, GATHER><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id,
+                                                                D.quarter, D.hist, btot, D.key2,
+                                                                D.idx2, static_cast<F4*>(D.pay2));
+    else
+        k_partition<M, GATHER><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id,
+                                                            D.quarter, D.hist, btot, D.key2, D.idx2,
+                                                            static_cast<Pay*>(D.pay2));
+    k_bucketsort<M, GATHER><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
+        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
+        D.split, D.tmp, D.perm, static_cast<Pay*>(D.payload), D.payq,
+        static_cast<const SimGeom*>(D.geom), B);
+}
+
 template <int M>
 hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const void* yv,
                            const void* zv, const void* dv, int64_t n, const int64_t* off,
-                           int32_t B, double edge, const double* edges, hipStream_t s)
+                           int32_t B, double edge, const double* edges, bool sorted_input,
+                           hipStream_t s)
 {
     using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
@@ -1071,20 +1113,10 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
                                                       L.nb_cap, D.start);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
-    if constexpr (sizeof(Pay) == sizeof(F4))
-        k_partition_lds<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
-                                                        D.hist, btot, D.key2, D.idx2,
-                                                        static_cast<F4*>(D.pay2));
+    if (sorted_input)
+        sort_passes<M, true>(L, D, x, y, z, d, n, B, nba, btot, s);
     else
-        k_partition<M><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id, D.quarter,
-                                                    D.hist, btot, D.key2, D.idx2,
-                                                    static_cast<Pay*>(D.pay2));
-    k_bucketsort<M><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
-        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
-        D.split, D.tmp,
-        D.perm,
-        static_cast<Pay*>(D.payload), D.payq,
-        batched ? nullptr : static_cast<const SimGeom*>(D.geom));
+        sort_passes<M, false>(L, D, x, y, z, d, n, B, nba, btot, s);
     return hipGetLastError();
 }
 
@@ -1114,13 +1146,17 @@ hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s)
 
 hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const void* y,
                              const void* z, const void* d, int64_t n, const int64_t* off,
-                             int32_t B, double edge, const double* edges, hipStream_t s)
+                             int32_t B, double edge, const double* edges, bool sorted_input,
+                             hipStream_t s)
 {
     switch (L.dtype) {
-    case MS_F32: return grid_build_mode<MS_F32>(L, D, x, y, z, d, n, off, B, edge, edges, s);
-    case MS_F64: return grid_build_mode<MS_F64>(L, D, x, y, z, d, n, off, B, edge, edges, s);
+    case MS_F32:
+        return grid_build_mode<MS_F32>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input, s);
+    case MS_F64:
+        return grid_build_mode<MS_F64>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input, s);
     case MS_F32_POS64:
-        return grid_build_mode<MS_F32_POS64>(L, D, x, y, z, d, n, off, B, edge, edges, s);
+        return grid_build_mode<MS_F32_POS64>(L, D, x, y, z, d, n, off, B, edge, edges,
+                                             sorted_input, s);
     default: return hipErrorInvalidValue;
     }
 }

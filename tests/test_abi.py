@@ -120,7 +120,10 @@ def test_workspace_struct_mirror_matches_header():
     assert [n for _, n in decl] == [n for n, _ in mirror]
     for (ty, name), (_, cty) in zip(decl, mirror):
         assert ctypes.sizeof(cty) == width[ty], name
-    assert ctypes.sizeof(_lib.ms_workspace) == sum(width[t] for t, _ in decl)
+    # no padding between fields; the end is padded to the struct's 8-byte alignment
+    offs = [getattr(_lib.ms_workspace, n).offset for _, n in decl]
+    assert offs == [sum(width[t] for t, _ in decl[:i]) for i in range(len(decl))]
+    assert ctypes.sizeof(_lib.ms_workspace) == (sum(width[t] for t, _ in decl) + 7) // 8 * 8
 
 
 def test_header_is_plain_c99(tmp_path):
