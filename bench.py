@@ -120,7 +120,7 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     gout = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(4))
     gkg = torch.empty(2, dtype=torch.float64, device="cuda")
     gin = tuple(torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3))
-    # contact-list length of the gather picked on this workload, outside the timed region
+    # launch shape of the gather (list length, block size) picked on this workload, outside the timed region
     from paper_2105_00039_amd import autotune
     ms.grid_build(ws, *t)
     ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
@@ -422,7 +422,7 @@ def time_batched(ms, torch, steps, warmup, seed=0, sorted_state=True):
     sec = a.elapsed_time(e) / 1e3
     return dict(value=n * steps / sec, unit="agent-steps/s", n_sims=b.n_sims, n_agents=n, steps=steps,
                 ms_per_step=sec / steps * 1e3, dtype="f32 force, f64 positions",
-                gather_list=tuning["choice"],
+                gather=dict(list=tuning["choice"][0], block=tuning["choice"][1]),
                 state_order="box-sorted slot order" if sorted_state else "caller order",
                 workload="batched256: sizes 10^U(3,5), 4-30 neighbours, kappa U[1,4], gamma U[0.5,2]")
 
@@ -611,7 +611,7 @@ def main():
             del pop, arrs
             b = time_batched(ms, torch, args.steps, args.warmup, sorted_state=args.order == "sorted")
             log(f"batched {b['n_sims']} simulations, {b['n_agents']} agents: {b['ms_per_step']:.3f} ms/step, "
-                f"{b['value']:.3e} agent-steps/s, list {b['gather_list']}")
+                f"{b['value']:.3e} agent-steps/s, gather {b['gather']}")
             return
         if args.workload == "clusters16M":
             del pop, arrs
@@ -692,20 +692,21 @@ def main():
         def plain(a, dt, **kw):
             sx, _, wx, _ = time_plain(ms, torch, a, dt, args.steps, args.warmup, graph=True,
                                       sorted_state=sorted_head, **kw)
-            return a[0].size * args.steps / sx, sx / args.steps * 1e3, wx.tuning["choice"]
+            c = wx.tuning["choice"]
+            return a[0].size * args.steps / sx, sx / args.steps * 1e3, dict(list=c[0], block=c[1])
 
         other = "f64" if args.dtype == "f32" else "f32"
         oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
         v, _, lst_ = plain(oarrs, other)
         extras[f"plain_{other}_n{args.neighbors:g}"] = v
-        extras[f"plain_{other}_n{args.neighbors:g}_gather_list"] = lst_
+        extras[f"plain_{other}_n{args.neighbors:g}_gather"] = lst_
         del oarrs
         for nb in (4.0, 30.0):
             p2 = workloads.uniform(N, mean_neighbors=nb, seed=args.seed)
             a2 = [a.astype(np_in) for a in p2.arrays()]
             v, _, lst_ = plain(a2, args.dtype)
             extras[f"plain_{args.dtype}_n{nb:g}"] = v
-            extras[f"plain_{args.dtype}_n{nb:g}_gather_list"] = lst_
+            extras[f"plain_{args.dtype}_n{nb:g}_gather"] = lst_
         # the same step with the state kept in the caller's order
         sc, _, _, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, graph=True,
                                  sorted_state=not sorted_head)
@@ -716,7 +717,7 @@ def main():
         del cl
         v, msps, lst_ = plain(carrs, "f32")
         extras["clusters16M_f32"] = v
-        extras["clusters16M_f32_gather_list"] = lst_
+        extras["clusters16M_f32_gather"] = lst_
         extras["clusters16M_f32_ms_per_step"] = msps
         del carrs
         torch.cuda.empty_cache()
@@ -753,7 +754,8 @@ def main():
                    "measured_neighbors": st["neighbors"], "contacts_per_agent": K,
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True,
-                   "gather_list": head_tuning["choice"], "gather_list_ms": head_tuning["ms"]},
+                   "gather": dict(list=head_tuning["choice"][0], block=head_tuning["choice"][1]),
+                   "gather_ms": head_tuning["ms"]},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
         "variants": extras, "fwd_bwd": fwd_bwd, "rollout_grad_adjoint262k": rollout_grad,
         "batched": batched, "host_state": host_state, "growing_population": growing,

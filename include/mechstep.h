@@ -104,8 +104,8 @@ typedef struct {
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
  * fields from n_agents to built are updated by the grid builds.  Treat them as
- * read-only; keep_forces, gather_list and sorted_input are the caller's to
- * set. */
+ * read-only; keep_forces, gather_list, gather_block and sorted_input are the
+ * caller's to set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -129,6 +129,11 @@ typedef struct {
                             populations; shorter ones leave LDS for more blocks
                             per CU.  Results are identical bit for bit; the
                             package's autotuner picks the faster one. */
+    int32_t gather_block; /* threads per block of the forward gather: 0 (set by
+                            ms_workspace_init; means 256), 128 or 256 (anything
+                            else: MS_EINVAL from the step calls).  Results are
+                            identical bit for bit; the autotuner picks it with
+                            gather_list. */
     int32_t sorted_input; /* 1: the next build's inputs are nearly box-sorted
                             (set by ms_mech_step_integrate_sorted, the batched
                             variant and ms_reorder, which write arrays in the

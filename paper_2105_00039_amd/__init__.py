@@ -71,7 +71,7 @@ class Workspace:
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
                  dtype: str = "f32", device=None, keep_forces: bool = False,
-                 gather_list: int = 0):
+                 gather_list: int = 0, gather_block: int = 0):
         self.lib = _lib.load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -90,6 +90,7 @@ class Workspace:
                                               self.code, _stream(self.device)))
         self.keep_forces = keep_forces
         self.gather_list = gather_list
+        self.gather_block = gather_block
         self.builds = 0   # grid builds issued on this workspace (the autograd layer checks it)
 
     @property
@@ -101,6 +102,16 @@ class Workspace:
     @gather_list.setter
     def gather_list(self, v: int):
         self.c.gather_list = int(v)
+
+    @property
+    def gather_block(self) -> int:
+        """Threads per block of the forward gather (0 = default 256, or 128 or
+        256); results do not depend on it, speed does (see autotune)."""
+        return int(self.c.gather_block)
+
+    @gather_block.setter
+    def gather_block(self, v: int):
+        self.c.gather_block = int(v)
 
     @property
     def sorted_input(self) -> bool:

@@ -49,7 +49,8 @@ class ms_workspace(ctypes.Structure):
                 ("max_sims", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("n_agents", ctypes.c_int64), ("n_sims", ctypes.c_int32),
                 ("built", ctypes.c_int32), ("keep_forces", ctypes.c_int32),
-                ("gather_list", ctypes.c_int32), ("sorted_input", ctypes.c_int32)]
+                ("gather_list", ctypes.c_int32), ("gather_block", ctypes.c_int32),
+                ("sorted_input", ctypes.c_int32)]
 
 
 class MechStepError(RuntimeError):

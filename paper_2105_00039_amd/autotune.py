@@ -1,12 +1,18 @@
-"""Autotuner of the forward gather's contact-list length.
+"""Autotuner of the forward gather's launch shape.
 
 The force gather keeps each lane's contacts in a list in LDS and drains it
-into the Eq. 1 work before it can overflow.  A longer list drains less often,
-which pays when agents have many contacts (dense or clustered populations,
-FP64); a shorter one leaves LDS for more resident blocks, which pays at low
-density.  Results are identical bit for bit for every length (the contacts
-are summed in the same order), so the choice is decided by timing the step
-on the caller's own workload, once per cache key.
+into the Eq. 1 work before it can overflow.  Two knobs shape the launch:
+
+* the list length (32 or 40 entries): a longer list drains less often, which
+  pays when agents have many contacts (dense or clustered populations,
+  FP64); a shorter one leaves LDS for more resident blocks;
+* the block size (256 or 128 threads): the list's LDS and the wavefronts
+  come in smaller units, so more blocks are resident and the batched step's
+  per-block simulation lookup covers fewer agents.
+
+Results are identical bit for bit for every choice (each agent's contacts
+are summed in the same order by one lane), so the choice is decided by
+timing the step on the caller's own workload, once per cache key.
 
 The default key is (dtype, agent count to the nearest power of two, mean box
 occupancy to the nearest half power of two, number of simulations).  Mean
@@ -23,7 +29,8 @@ import torch
 
 from . import grid_info
 
-CHOICES = (32, 40)
+# (contact-list length, threads per block); the first is the library default
+CHOICES = ((32, 256), (40, 256), (32, 128), (40, 128))
 
 
 def default_key(ws) -> str:
@@ -46,25 +53,38 @@ def _load(cache):
     return {}, path
 
 
+def _as_choice(v):
+    """A cached entry as a (list, block) pair (older caches hold the list only)."""
+    if isinstance(v, (list, tuple)):
+        return (int(v[0]), int(v[1]))
+    return (int(v), 256)
+
+
+def _set(ws, c):
+    ws.gather_list, ws.gather_block = c
+
+
 def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache=None,
          margin: float = 0.02) -> dict:
-    """Pick the fastest contact-list length for ``step`` (a callable running one
-    force step on the workspace's current build, e.g. ``lambda: mech_step(ws,
-    params, out=out)``) and set it on ``ws``.  The first of ``choices`` (the
-    library default) is kept unless another is faster by more than ``margin``,
-    so a tie does not flip the choice from run to run.
+    """Pick the fastest (list length, block size) for ``step`` (a callable
+    running one force step on the workspace's current build, e.g. ``lambda:
+    mech_step(ws, params, out=out)``) and set it on ``ws``.  The first of
+    ``choices`` (the library default) is kept unless another is faster by more
+    than ``margin``, so a tie does not flip the choice from run to run.
 
     cache: None, a dict, or the path of a JSON file (read if present, written
-    after a timed choice).  Returns {"key", "choice", "source": "cache" |
-    "timed", "ms": {length: mean ms per step}}."""
+    after a timed choice).  Returns {"key", "choice": (list, block), "source":
+    "cache" | "timed", "ms": {"list/block": mean ms per step}}."""
+    choices = tuple(_as_choice(c) for c in choices)
     key = key or default_key(ws)
     table, path = _load(cache)
-    if key in table and int(table[key]) in choices:
-        ws.gather_list = int(table[key])
-        return dict(key=key, choice=ws.gather_list, source="cache", ms={})
+    if key in table and _as_choice(table[key]) in choices:
+        c = _as_choice(table[key])
+        _set(ws, c)
+        return dict(key=key, choice=c, source="cache", ms={})
     times = {}
     for c in choices:
-        ws.gather_list = c
+        _set(ws, c)
         step()                                   # warm-up of this variant
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -77,9 +97,10 @@ def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache
     best = min(times, key=times.get)
     if times[choices[0]] <= times[best] * (1.0 + margin):
         best = choices[0]
-    ws.gather_list = best
-    table[key] = best
+    _set(ws, best)
+    table[key] = list(best)
     if path is not None:
         with open(path, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
-    return dict(key=key, choice=best, source="timed", ms=times)
+    return dict(key=key, choice=best, source="timed",
+                ms={f"{c[0]}/{c[1]}": t for c, t in times.items()})

@@ -118,6 +118,7 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->keep_forces = 0;
     ws->gather_list = 0;
     ws->sorted_input = 0;
+    ws->gather_block = 0;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -167,10 +168,16 @@ ms_status ms_grid_build_batched(ms_workspace* ws, const void* x, const void* y, 
                         "ms_grid_build_batched");
 }
 
-// Contact-list length of the forward gather chosen by the workspace.
+// Contact-list length and block size of the forward gather chosen by the
+// workspace.
 static int gather_list(const ms_workspace* ws)
 {
     return ws->gather_list == ms::kLongList ? ms::kLongList : ms::kMaxContacts;
+}
+
+static int gather_block(const ms_workspace* ws)
+{
+    return ws->gather_block == ms::kForceBlockSmall ? ms::kForceBlockSmall : ms::kBlock;
 }
 
 static ms_status step_common(const ms_workspace* ws, int want_built, const char* who)
@@ -181,6 +188,10 @@ static ms_status step_common(const ms_workspace* ws, int want_built, const char*
         ws->gather_list != ms::kLongList)
         return fail(MS_EINVAL, "%s: gather_list must be 0, %d or %d", who, ms::kMaxContacts,
                     ms::kLongList);
+    if (ws->gather_block != 0 && ws->gather_block != ms::kForceBlockSmall &&
+        ws->gather_block != ms::kBlock)
+        return fail(MS_EINVAL, "%s: gather_block must be 0, %d or %d", who, ms::kForceBlockSmall,
+                    ms::kBlock);
     if (ws->built != want_built)
         return fail(MS_EINVAL, "%s: workspace holds no %s grid build", who,
                     want_built == 1 ? "plain" : "batched");
@@ -200,7 +211,7 @@ ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, voi
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
                                       dz, nullptr, nullptr, nullptr, ws->keep_forces != 0,
-                                      gather_list(ws), as_stream(stream)),
+                                      gather_list(ws), gather_block(ws), as_stream(stream)),
                      who);
 }
 
@@ -230,6 +241,7 @@ ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, voi
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
                                       dz, x, y, z, ws->keep_forces != 0, gather_list(ws),
+                                      gather_block(ws),
                                       as_stream(stream)),
                      who);
 }
@@ -274,6 +286,7 @@ static ms_status step_sorted_common(ms_workspace* ws, bool batched, const ms_par
                                       batched, batched ? nullptr : p, batched ? p : nullptr, dx, dy,
                                       dz, nullptr, nullptr, nullptr,
                                       !batched && ws->keep_forces != 0, gather_list(ws),
+                                      gather_block(ws),
                                       as_stream(stream), &so),
                      who);
 }
@@ -310,7 +323,7 @@ ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, 
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
                                       params, dx, dy, dz, nullptr, nullptr, nullptr, false,
-                                      gather_list(ws), as_stream(stream)),
+                                      gather_list(ws), gather_block(ws), as_stream(stream)),
                      who);
 }
 
@@ -328,6 +341,7 @@ ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
                                       params, dx, dy, dz, x, y, z, false, gather_list(ws),
+                                      gather_block(ws),
                                       as_stream(stream)),
                      who);
 }
@@ -627,7 +641,7 @@ ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, cons
         e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, false, s);
     if (e == hipSuccess && n > 0)
         e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
-                             false, ms::kMaxContacts, s);
+                             false, ms::kMaxContacts, ms::kBlock, s);
     if (e == hipSuccess && dev_error) e = ms::launch_error_copy(D, dev_error, s);
     return check_hip(e, who);
 }

@@ -23,6 +23,7 @@ constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
+constexpr int kForceBlockSmall = 128; // the smaller block the forward gather may use
 // Quantised slot copy of plain builds (the gather's candidate test): quanta
 // per box edge, and the margin (in quanta) added to the summed radii.
 constexpr int kQuantScale = 8192;

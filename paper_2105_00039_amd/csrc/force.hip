@@ -33,8 +33,8 @@ struct SortedOut {
 // Plain FP64 builds ask for at least 4 wavefronts per SIMD (at most 128
 // VGPRs, against 131 otherwise): with 3 the gather's loads are hidden worse
 // (force kernel at 2M agents, n~12: 309 -> 287 us).
-template <int M, bool BATCHED, int LIST, bool SORTED>
-__global__ __launch_bounds__(kBlock)
+template <int M, bool BATCHED, int LIST, bool SORTED, int NT>
+__global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_force(const typename Mode<M>::Pay* __restrict__ pay,
                                                   const int32_t* __restrict__ start,
                                                   const uint32_t* __restrict__ split,
@@ -52,7 +52,7 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     using Real = typename Mode<M>::Real;
     using In = typename Mode<M>::In;
     using Pay = typename Mode<M>::Pay;
-    __shared__ uint32_t lst[LIST * kBlock];
+    __shared__ uint32_t lst[LIST * NT];
     if (hdr->error) return;
     // forces kept for the backward step: record which build and parameters
     // they belong to (the backward uses them only on a match)
@@ -60,17 +60,17 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
         hdr->fwd_gen = hdr->build_gen;
         hdr->fwd_params = p1;
     }
-    const int64_t k0 = (int64_t)xcd_block() * kBlock;
+    const int64_t k0 = (int64_t)xcd_block() * NT;
     const int64_t k = k0 + threadIdx.x;
     int s = 0;
-    if (BATCHED) s = block_sim(off, B, n, k0, k, reinterpret_cast<int*>(lst));
+    if (BATCHED) s = block_sim<NT>(off, B, n, k0, k, reinterpret_cast<int*>(lst));
     if (k >= n) return;
     const SimGeom g = geom[s];
     const ms_params P = BATCHED ? pB[s] : p1;
     const Pay pi = pay[k];
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
-    force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
+    force_sum<Real, Pay, LIST, NT>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                     pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
                                     preq_of(payq, k), fx, fy, fz);
     if (fsave) {
@@ -298,39 +298,56 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
     for (; i < n4; i += stride) dst[i] = src[i];
 }
 
-template <int M, bool BATCHED, int LIST, bool SORTED>
+template <int M, bool BATCHED, int LIST, bool SORTED, int NT>
 void launch_k_force(const Dev& D, int64_t n, int32_t B, const ms_params& p1, const ms_params* p_dev,
                     typename Mode<M>::Pay* rec, typename Mode<M>::Pay* fs,
                     const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, hipStream_t s)
 {
     using Pay = typename Mode<M>::Pay;
-    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    k_force<M, BATCHED, LIST, SORTED><<<nb, kBlock, 0, s>>>(
+    const unsigned nb = (unsigned)((n + NT - 1) / NT);
+    k_force<M, BATCHED, LIST, SORTED, NT><<<nb, NT, 0, s>>>(
         static_cast<const Pay*>(D.payload), D.start, D.split, D.perm, D.geom, BATCHED ? D.off : nullptr,
         B, n, p1, p_dev, D.hdr, rec, fs, D.payq, so);
 }
 
+template <int M, bool BATCHED, bool SORTED, int NT>
+void launch_k_force_nt(const Dev& D, int64_t n, int32_t B, const ms_params& p1,
+                       const ms_params* p_dev, typename Mode<M>::Pay* rec,
+                       typename Mode<M>::Pay* fs,
+                       const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, int list,
+                       hipStream_t s)
+{
+    if (list == kLongList)
+        launch_k_force<M, BATCHED, kLongList, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, s);
+    else
+        launch_k_force<M, BATCHED, kMaxContacts, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, s);
+}
+
+// The forward gather's launch shape chosen per workspace: contact-list length
+// (kMaxContacts or kLongList) and threads per block (kForceBlockSmall or kBlock).
 template <int M, bool SORTED>
 void launch_k_force_list(const Dev& D, int64_t n, int32_t B, bool batched, const ms_params& p1,
                          const ms_params* p_dev, typename Mode<M>::Pay* rec,
                          typename Mode<M>::Pay* fs,
                          const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, int list,
-                         hipStream_t s)
+                         int nt, hipStream_t s)
 {
-    if (batched && list == kLongList)
-        launch_k_force<M, true, kLongList, SORTED>(D, n, B, p1, p_dev, rec, nullptr, so, s);
+    if (batched && nt == kForceBlockSmall)
+        launch_k_force_nt<M, true, SORTED, kForceBlockSmall>(D, n, B, p1, p_dev, rec, nullptr, so,
+                                                             list, s);
     else if (batched)
-        launch_k_force<M, true, kMaxContacts, SORTED>(D, n, B, p1, p_dev, rec, nullptr, so, s);
-    else if (list == kLongList)
-        launch_k_force<M, false, kLongList, SORTED>(D, n, 1, p1, nullptr, rec, fs, so, s);
+        launch_k_force_nt<M, true, SORTED, kBlock>(D, n, B, p1, p_dev, rec, nullptr, so, list, s);
+    else if (nt == kForceBlockSmall)
+        launch_k_force_nt<M, false, SORTED, kForceBlockSmall>(D, n, 1, p1, nullptr, rec, fs, so,
+                                                              list, s);
     else
-        launch_k_force<M, false, kMaxContacts, SORTED>(D, n, 1, p1, nullptr, rec, fs, so, s);
+        launch_k_force_nt<M, false, SORTED, kBlock>(D, n, 1, p1, nullptr, rec, fs, so, list, s);
 }
 
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                      void* dz, void* px, void* py, void* pz, bool keep, int list,
+                      void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
                       const SortedState* sorted, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
@@ -350,10 +367,10 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
         so.dx = X; so.dy = Y; so.dz = Z;
         so.xi = static_cast<const In*>(sorted->x_in); so.yi = static_cast<const In*>(sorted->y_in);
         so.zi = static_cast<const In*>(sorted->z_in); so.di = static_cast<const In*>(sorted->d_in);
-        launch_k_force_list<M, true>(D, n, B, batched, p1, p_dev, A, fs, so, list, s);
+        launch_k_force_list<M, true>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, s);
         return hipGetLastError();
     }
-    launch_k_force_list<M, false>(D, n, B, batched, p1, p_dev, A, fs, so, list, s);
+    launch_k_force_list<M, false>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, s);
     if (px) {
         k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),
                                                              static_cast<In*>(py),
@@ -402,19 +419,19 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, void* px, void* py, void* pz, bool keep, int list,
+                        void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
                         hipStream_t s, const SortedState* sorted)
 {
     switch (L.dtype) {
     case MS_F32:
         return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, sorted, s);
+                                  list, nt, sorted, s);
     case MS_F64:
         return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, sorted, s);
+                                  list, nt, sorted, s);
     case MS_F32_POS64:
         return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz,
-                                        keep, list, sorted, s);
+                                        keep, list, nt, sorted, s);
     default: return hipErrorInvalidValue;
     }
 }

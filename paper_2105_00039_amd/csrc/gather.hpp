@@ -28,11 +28,12 @@ __device__ __forceinline__ double rdiv(double a, double b) { return a / b; }
 // each thread searches only between them.  s_range: two ints of LDS, free
 // again when this returns (the gather kernels lend the first entries of
 // their contact lists, so no extra LDS limits how many blocks fit a CU).
+template <int NT = kBlock>
 __device__ __forceinline__ int block_sim(const int64_t* __restrict__ off, int32_t B, int64_t n,
                                          int64_t first, int64_t i, int* s_range)
 {
     if (threadIdx.x == 0) {
-        const int64_t last = (first + kBlock < n ? first + kBlock : n) - 1;
+        const int64_t last = (first + NT < n ? first + NT : n) - 1;
         s_range[0] = find_sim(off, 0, B, first);
         s_range[1] = find_sim(off, 0, B, last);
     }
@@ -112,7 +113,8 @@ __device__ __forceinline__ Real len2(Real ux, Real uy, Real uz)
 
 // Force of one listed pair (Eq. 1) added to a; nothing unless the spheres
 // overlap (delta > 0) and the centres differ.  FP32: 1/l from rsq, rho from
-// a reciprocal.  Each pair's term is rounded before it is added (multiply,
+// a reciprocal; coincident centres give rsq(0) = inf and a NaN delta, which
+// fails delta > 0.  Each pair's term is rounded before it is added (multiply,
 // then add): two pairs that mirror each other then cancel exactly, as the
 // oracle's do (a fused multiply-add would leave the rounding error of the
 // first product behind).
@@ -124,7 +126,7 @@ __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float k
     const float rs = pi.w + q.w;
     const float il = __builtin_amdgcn_rsqf(l2);
     const float delta = fmad(-l2, il, rs);
-    if (delta > 0.0f && l2 > 0.0f) {
+    if (delta > 0.0f) {
         const float rho = pi.w * q.w * __builtin_amdgcn_rcpf(rs);
         const float sv = fmad(kap, delta, -gam * __builtin_amdgcn_sqrtf(rho * delta));
         const float sl = sv * il;
@@ -296,7 +298,8 @@ __device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
 // Two phases keep the wavefront busy.  The scan walks the 9 trimmed runs;
 // four candidates are loaded before any is tested (offsets clamped into the
 // run, surplus tests masked), and each passing candidate's offset is appended
-// to this lane's list in LDS (`lst`, stride kBlock) without branching (the
+// to this lane's list in LDS (`lst`, stride NT, the block size) without
+// branching (the
 // slot is always written, the cursor advances on a hit).  The pair work then
 // runs over the list, four payload loads in flight at a time.  The list is
 // drained (by the whole wavefront at once) before a group of four could
@@ -304,7 +307,7 @@ __device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
 // Offsets are 32-bit: a workspace holds fewer than 2^32 payload bytes.
 // The scan reads the quantised slot copy `pre`; the list holds copy offsets,
 // scaled to payload offsets when drained.
-template <typename Real, typename Pay, int LIST = kMaxContacts, typename OnPair>
+template <typename Real, typename Pay, int LIST = kMaxContacts, int NT = kBlock, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
@@ -325,7 +328,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
             Pay q[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t v = lst[(t + u) * kBlock];
+                const uint32_t v = lst[(t + u) * NT];
                 o[u] = (t + u < cnt) ? (v << SH) : self_off;
             }
             pin4(o);
@@ -338,7 +341,7 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
     };
     auto test = [&](uint2 q, uint32_t off, bool live) {
         pin(q);
-        lst[cnt * kBlock] = off;
+        lst[cnt * NT] = off;
         cnt += (int)(live & quant_hit(pre, q));
     };
     using SPay = uint2;
@@ -372,8 +375,8 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
 
 // Eq. 1 summed over every candidate in contact with agent `pi`, in canonical
 // order (contact_force drops non-overlapping pairs and the agent itself).
-// LIST: length of the per-lane contact list `lst` (stride kBlock).
-template <typename Real, typename Pay, int LIST = kMaxContacts>
+// LIST: length of the per-lane contact list `lst` (stride NT, the block size).
+template <typename Real, typename Pay, int LIST = kMaxContacts, int NT = kBlock>
 __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& pi,
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
@@ -382,7 +385,7 @@ __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& p
                                           Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay, LIST>(g, c, pi, self_off, start, split, pay, lst, pre,
+    scan_contacts<Real, Pay, LIST, NT>(g, c, pi, self_off, start, split, pay, lst, pre,
                                         [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });

@@ -37,10 +37,11 @@ struct SortedState {
 // then be null.  sorted non-null: the sorted-state step (dx/dy/dz, if given,
 // in slot order; px/py/pz unused).  keep (single only): also store the
 // forces for the backward step.  list: contact-list length of the gather
-// (kMaxContacts or kLongList).
+// (kMaxContacts or kLongList); nt: threads per block of the gather
+// (kForceBlockSmall or kBlock).
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
-                        void* dz, void* px, void* py, void* pz, bool keep, int list,
+                        void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
                         hipStream_t s, const SortedState* sorted = nullptr);
 
 // Backward step; list: contact-list length of its gathers (as launch_force).

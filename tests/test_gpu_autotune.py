@@ -1,8 +1,9 @@
-"""The contact-list length of the forward gather (the autotuner's knob) does
-not change any result: plain, fused and batched steps and the backward are
-bitwise identical for every allowed length; the tuner picks an allowed
-length, caches it under its key (dict or JSON file) and reuses it; other
-lengths are rejected through the C ABI."""
+"""The forward gather's launch shape (the autotuner's knobs: contact-list
+length and block size) does not change any result: plain, fused, sorted and
+batched steps and the backward are bitwise identical for every allowed
+choice; the tuner picks an allowed (length, block) pair, caches it under its
+key (dict or JSON file) and reuses it; other values are rejected through the
+C ABI."""
 import json
 
 import numpy as np
@@ -38,7 +39,7 @@ def population(name):
 
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("case", ["uniform20000_n30", "clusters20000_dense"])
-def test_list_length_does_not_change_results(case, mode):
+def test_launch_shape_does_not_change_results(case, mode):
     arrs = population(case)
     n = len(arrs[0])
     ws = ms.Workspace(n, dtype=mode)
@@ -46,31 +47,34 @@ def test_list_length_does_not_change_results(case, mode):
     ms.grid_build(ws, *t)
     g = [torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3)]
     res = {}
-    for L in (32, 40):
-        ws.gather_list = L
+    for c in autotune.CHOICES:
+        ws.gather_list, ws.gather_block = c
         D = [a.clone() for a in ms.mech_step(ws, P)]
         G = [a.clone() for a in ms.mech_step_backward(ws, P, *g)[:4]]
         pos = [a.clone() for a in t[:3]]
         ms.mech_step_integrate(ws, P, *pos)
-        res[L] = D + G + pos
+        so = [a.clone() for a in ms.mech_step_integrate_sorted(ws, P, *t)]
+        res[c] = D + G + pos + so
     ms.device_status(ws)
-    for a, b in zip(res[32], res[40]):
-        assert torch.equal(a, b)
+    for c in autotune.CHOICES[1:]:
+        for a, b in zip(res[autotune.CHOICES[0]], res[c]):
+            assert torch.equal(a, b), c
 
 
-def test_list_length_batched():
+def test_launch_shape_batched():
     b = workloads.batched(n_sims=10, log10_min=2.0, log10_max=3.7, seed=43)
     prms = [dict(P, kappa=float(k), gamma=float(gm)) for k, gm in zip(b.kappa, b.gamma)]
     Pd = ms.params_tensor(prms, "cuda")
     ws = ms.Workspace(b.n, max_sims=b.n_sims, dtype="f32_pos64")
     ms.grid_build_batched(ws, *dev(b.arrays(), "f32_pos64"), ms.BatchSpec(b.offsets))
     out = {}
-    for L in (32, 40):
-        ws.gather_list = L
-        out[L] = [a.clone() for a in ms.mech_step_batched(ws, Pd)]
+    for c in autotune.CHOICES:
+        ws.gather_list, ws.gather_block = c
+        out[c] = [a.clone() for a in ms.mech_step_batched(ws, Pd)]
     ms.device_status(ws)
-    for a, c in zip(out[32], out[40]):
-        assert torch.equal(a, c)
+    for c in autotune.CHOICES[1:]:
+        for a, b in zip(out[autotune.CHOICES[0]], out[c]):
+            assert torch.equal(a, b), c
 
 
 def test_tuner_picks_caches_and_rejects(tmp_path):
@@ -86,19 +90,24 @@ def test_tuner_picks_caches_and_rejects(tmp_path):
     table = {}
     r = autotune.tune(ws, step, cache=table)
     assert r["source"] == "timed" and r["choice"] in autotune.CHOICES
-    assert ws.gather_list == r["choice"] and table[r["key"]] == r["choice"]
-    ws.gather_list = 0
+    assert (ws.gather_list, ws.gather_block) == r["choice"]
+    assert tuple(table[r["key"]]) == r["choice"] and len(r["ms"]) == len(autotune.CHOICES)
+    ws.gather_list, ws.gather_block = 0, 0
     r2 = autotune.tune(ws, step, cache=table)
-    assert r2["source"] == "cache" and ws.gather_list == r["choice"]
+    assert r2["source"] == "cache" and (ws.gather_list, ws.gather_block) == r["choice"]
     path = tmp_path / "tune.json"
     r3 = autotune.tune(ws, step, key="custom", cache=path)
-    assert r3["source"] == "timed" and json.loads(path.read_text())["custom"] == r3["choice"]
+    assert r3["source"] == "timed" and tuple(json.loads(path.read_text())["custom"]) == r3["choice"]
     r4 = autotune.tune(ws, step, key="custom", cache=path)
     assert r4["source"] == "cache" and r4["choice"] == r3["choice"]
     ws.gather_list = 33
     with pytest.raises(ms.MechStepError) as ei:
         ms.mech_step(ws, P)
     assert ei.value.status == ms._lib.MS_EINVAL
-    ws.gather_list = 0
+    ws.gather_list, ws.gather_block = 0, 64
+    with pytest.raises(ms.MechStepError) as ei:
+        ms.mech_step(ws, P)
+    assert ei.value.status == ms._lib.MS_EINVAL
+    ws.gather_block = 0
     ms.mech_step(ws, P)
     ms.device_status(ws)
