@@ -30,6 +30,8 @@
 // gradient to a running sum and the kappa/gamma gradients to running sums:
 // one backward step of a rollout p_{t+1} = p_t + Delta(p_t).
 #include "gather.hpp"
+
+#include <type_traits>
 #include "launch.hpp"
 
 namespace ms {
@@ -211,15 +213,33 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             const Real ux = pi.x - q.x, uy = pi.y - q.y, uz = pi.z - q.z;
             const Real l2 = len2(ux, uy, uz);
             const Real rs = pi.w + q.w;
-            const Real l = fsqrt(l2);
-            const Real delta = rs - l;
-            if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
-            const Real il = rdiv((Real)1, l);
+            Real delta, il, rho, sq, h, wj;
+            if constexpr (std::is_same<Real, float>::value) {
+                // the forward's contact test (same overlap, so the same
+                // contacts), and three hardware reciprocal square roots or
+                // reciprocals per pair: 1/l, 1/(r_i + r_j), 1/sqrt(rho delta)
+                il = __builtin_amdgcn_rsqf(l2);
+                delta = fmad(-l2, il, rs);
+                if (!(delta > 0.0f)) return;   // coincident centres: NaN delta
+                const float ircs = __builtin_amdgcn_rcpf(rs);
+                rho = pi.w * q.w * ircs;
+                const float rd = rho * delta;
+                const float irq = __builtin_amdgcn_rsqf(rd);
+                sq = rd * irq;
+                h = 0.5f * irq;
+                wj = q.w * ircs;
+            } else {
+                const Real l = fsqrt(l2);
+                delta = rs - l;
+                if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
+                il = (Real)1 / l;
+                rho = pi.w * q.w / rs;
+                sq = fsqrt(rho * delta);
+                h = (Real)0.5 / sq;
+                wj = q.w / rs;
+            }
             const Real ex = ux * il, ey = uy * il, ez = uz * il;
-            const Real rho = rdiv(pi.w * q.w, rs);
-            const Real sq = fsqrt(rho * delta);
             const Real sv = kap * delta - gam * sq;
-            const Real h = rdiv((Real)0.5, sq);
             const Real s_d = kap - gam * rho * h;
             const Real s_r = -gam * delta * h;
             const Real wx = fi.x - fj.x, wy = fi.y - fj.y, wz = fi.z - fj.z;
@@ -228,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
             px += sl * (wx - ex * qv) - s_d * qv * ex;
             py += sl * (wy - ey * qv) - s_d * qv * ey;
             pz += sl * (wz - ez * qv) - s_d * qv * ez;
-            rb += qv * (s_d + s_r * (q.w * q.w) / (rs * rs));
+            rb += qv * (s_d + s_r * (wj * wj));
             const Real eF = ex * fi.x + ey * fi.y + ez * fi.z;
             kbl += delta * eF;
             gbl -= sq * eF;
