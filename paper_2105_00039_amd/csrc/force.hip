@@ -68,6 +68,13 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     const SimGeom g = geom[s];
     const ms_params P = BATCHED ? pB[s] : p1;
     const Pay pi = pay[k];
+    // sorted-state step of FP64 positions: the master state of this slot is
+    // read through perm, issued here so its latency hides behind the gather
+    In mx = 0, my = 0, mz = 0, md = 0;
+    if constexpr (SORTED && M == MS_F32_POS64) {
+        const int32_t o = perm[k];
+        mx = so.xi[o]; my = so.yi[o]; mz = so.zi[o]; md = so.di[o];
+    }
     const Cell c = cell_of<Real>(g, pi.x, pi.y, pi.z);
     Real fx, fy, fz;
     force_sum<Real, Pay, LIST, NT>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
@@ -85,8 +92,7 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
         // added): the step equals the caller-order step renumbered
         In px, py, pz, pd;
         if constexpr (M == MS_F32_POS64) {
-            const int32_t o = perm[k];
-            px = so.xi[o]; py = so.yi[o]; pz = so.zi[o]; pd = so.di[o];
+            px = mx; py = my; pz = mz; pd = md;
         } else {
             px = pi.x; py = pi.y; pz = pi.z;
             pd = (In)2 * pi.w;   // the build stored d/2: exact for every normal d
