@@ -536,9 +536,10 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
         sb = hdr->sb;
         nbk = hdr->nb;
     } else {
-        // One simulation: every block reduces the bounds partials itself (a
-        // launch of its own costs more), block 0 publishes the geometry and
-        // the build header for the later passes.
+        // One simulation: up to kGeomSplit bounds partials every block
+        // reduces them itself (a launch of its own costs more at that size)
+        // and block 0 publishes the geometry and the build header for the
+        // later passes; above it k_geometry1 has done both.
         if (PRE) {
             // geometry and header published by k_geometry1
             if (threadIdx.x == 0) {
