@@ -1003,27 +1003,34 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
                 inv[bs + r] = j;
             }
             __syncthreads();
-            int jj[U];
+            // FP64 inputs are written in two halves (fewer 8-byte values in
+            // flight, as in the staged path)
+            constexpr int HALVES = 2;
+            constexpr int UH = U / HALVES;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = threadIdx.x + u * kSortThreads;
-                jj[u] = p < cn ? inv[p] : 0;
-                pm[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
-            }
-            typename Mode<M>::Pay q[U];
-            int bx[U];
+            for (int hh = 0; hh < HALVES; ++hh) {
+                int jj[UH], pw[UH];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                q[u] = src.get(s0 + pm[u], mem[jj[u]]);
-                bx[u] = b0 + (key2[s0 + pm[u]] >> 2);
-            }
+                for (int u = 0; u < UH; ++u) {
+                    const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
+                    jj[u] = p < cn ? inv[p] : 0;
+                    pw[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
+                }
+                typename Mode<M>::Pay q[UH];
+                int bx[UH];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = threadIdx.x + u * kSortThreads;
-                if (p < cn) {
-                    perm[s0 + cs + p] = mem[jj[u]];
-                    pay[s0 + cs + p] = q[u];
-                    s32.put(s0 + cs + p, q[u], bx[u]);
+                for (int u = 0; u < UH; ++u) {
+                    q[u] = src.get(s0 + pw[u], mem[jj[u]]);
+                    bx[u] = b0 + (key2[s0 + pw[u]] >> 2);
+                }
+#pragma unroll
+                for (int u = 0; u < UH; ++u) {
+                    const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
+                    if (p < cn) {
+                        perm[s0 + cs + p] = mem[jj[u]];
+                        pay[s0 + cs + p] = q[u];
+                        s32.put(s0 + cs + p, q[u], bx[u]);
+                    }
                 }
             }
             __syncthreads();
@@ -1053,15 +1060,13 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
     }
 }
 
-// FP32 payloads ask for 6 wavefronts per SIMD (at most 80 VGPRs, against 94
-// to 96 otherwise, a few spilled): three 512-thread blocks then fit a CU, so
-// the 2M-agent build's ~740 buckets run in one round instead of ~1.4 (bucket
-// sort 42.8 -> 33.9 us on the sorted state).  The FP64 kernel and the gather
-// mode of FP64 positions (122 VGPRs; 67 would spill, measured 202 -> 255 us
-// on the 256-simulation batch) keep 2 blocks per CU.
+// Six wavefronts per SIMD (at most 80 VGPRs; the slot-order writes go out in
+// two halves so that no mode needs more): three 512-thread blocks then fit a
+// CU, so the 2M-agent build's ~740 buckets run in one round instead of ~1.4
+// (bucket sort 42.8 -> 33.9 us on the sorted state).
 template <int M, bool GATHER>
 __global__ __launch_bounds__(kSortThreads)
-__attribute__((amdgpu_waves_per_eu(M == MS_F64 || (M == MS_F32_POS64 && GATHER) ? 1 : 6)))
+__attribute__((amdgpu_waves_per_eu(6)))
 void k_bucketsort(const Header* __restrict__ hdr,
                                                              const int32_t* __restrict__ key2,
                                                              const int32_t* __restrict__ idx2,
@@ -1202,30 +1207,37 @@ void k_bucketsort(const Header* __restrict__ hdr,
     // 5. write the sorted bucket in slot order (loads issued before the stores)
     if (s1 > s0) {   // block-uniform; padding lanes read slot s0
         const SlotQ s32(payq, geom, s_sims[0], s_sims[1]);
-        constexpr int U = kSortStage / kSortThreads;
+        constexpr int UA = kSortStage / kSortThreads;
+        // FP64 inputs are written in two halves, so that half as many 8-byte
+        // values are in flight (fewer VGPRs, more blocks per CU)
+        constexpr int HALVES = 2;
+        constexpr int U = UA / HALVES;
         const int cnt = s1 - s0;
-        int e[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = threadIdx.x + u * kSortThreads;
-            e[u] = s0 + (p < cnt ? inv[p] : 0);
-        }
-        int32_t id[U], bx[U];
-        typename Mode<M>::Pay q[U];
+        for (int hh = 0; hh < HALVES; ++hh) {
+            int e[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            id[u] = idx2[e[u]];
-            bx[u] = b0 + (key2[e[u]] >> 2);
-        }
+            for (int u = 0; u < U; ++u) {
+                const int p = threadIdx.x + (hh * U + u) * kSortThreads;
+                e[u] = s0 + (p < cnt ? inv[p] : 0);
+            }
+            int32_t id[U], bx[U];
+            typename Mode<M>::Pay q[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = src.get(e[u], id[u]);
+            for (int u = 0; u < U; ++u) {
+                id[u] = idx2[e[u]];
+                bx[u] = b0 + (key2[e[u]] >> 2);
+            }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = threadIdx.x + u * kSortThreads;
-            if (p < cnt) {
-                perm[s0 + p] = id[u];
-                pay[s0 + p] = q[u];
-                s32.put(s0 + p, q[u], bx[u]);
+            for (int u = 0; u < U; ++u) q[u] = src.get(e[u], id[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = threadIdx.x + (hh * U + u) * kSortThreads;
+                if (p < cnt) {
+                    perm[s0 + p] = id[u];
+                    pay[s0 + p] = q[u];
+                    s32.put(s0 + p, q[u], bx[u]);
+                }
             }
         }
     }
