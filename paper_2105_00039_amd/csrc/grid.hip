@@ -448,6 +448,23 @@ __device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t 
 // launch of its own (k_geometry1) rather than in every histogram block.
 constexpr int kGeomSplit = 1024;
 
+// Zero the (bucket x tile) count matrix of a large single build, whose
+// histogram then writes only nonzero counts.  Sized by the bucket count the
+// geometry reduction published.
+__global__ __launch_bounds__(kBlock) void k_clear_hist(const Header* __restrict__ hdr,
+                                                       int32_t* __restrict__ hist, int32_t nblk)
+{
+    if (hdr->error) return;
+    const int64_t total = (int64_t)hdr->nb * nblk;
+    const int64_t n4 = total / 4;
+    int4* h4 = reinterpret_cast<int4*>(hist);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride)
+        h4[i] = make_int4(0, 0, 0, 0);
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride)
+        hist[i] = 0;
+}
+
 // Single simulation with many bounds partials (more than kGeomSplit): one
 // block of 1,024 threads reduces them all (a few loads per thread, issued
 // together) and publishes geometry and header once, instead of every
@@ -582,7 +599,11 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbk; b += kTileThreads)
-        hist[(int64_t)b * gridDim.x + tile] = h[b];
+        // large single builds (PRE) cleared the matrix beforehand and write
+        // only the buckets this tile touches: a tile of box-sorted input
+        // falls into a few buckets, and each 4-byte store of a zero column
+        // entry costs a whole memory sector
+        if (!PRE || h[b] != 0) hist[(int64_t)b * gridDim.x + tile] = h[b];
 }
 
 // One block per bucket: exclusive scan along its row of per-block counts.
@@ -1326,6 +1347,7 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     else if (nbb > (unsigned)kGeomSplit) {
         k_geometry1<<<1, 1024, 0, s>>>(D.bpart, n, edge, L.max_boxes, L.nb_cap, D.geom, D.hdr,
                                        D.start);
+        k_clear_hist<<<1024, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba);
         k_hist<M, false, true><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr,
                                                             D.box_id, D.quarter, D.hist, D.bpart,
                                                             edge, L.max_boxes, L.nb_cap, D.start);
