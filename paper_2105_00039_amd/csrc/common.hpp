@@ -21,6 +21,7 @@ constexpr int kSBMin = 6;             // bucket = 2^SB consecutive boxes, SB in 
 constexpr int kSBMax = 12;
 constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
+constexpr int kSortStage = 4096;      // buckets up to this many agents are sorted in LDS
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
 constexpr int kForceBlockSmall = 128; // the smaller block the forward gather may use
@@ -58,7 +59,8 @@ struct Header {
     uint32_t build_gen;    // incremented by every build
     uint32_t fwd_gen;      // build_gen of the forward step that kept its forces
     ms_params fwd_params;  // parameters of that forward step
-    uint8_t pad[256 - 96];
+    uint32_t nchunk;       // chunk descriptors of the current large build's oversized buckets
+    uint8_t pad[256 - 100];
 };
 static_assert(sizeof(Header) == 256, "header size");
 
@@ -95,7 +97,7 @@ template <> struct Mode<MS_F32_POS64> { using In = double; using Real = float;  
 // Byte offsets of every region of the workspace buffer.
 struct Layout {
     size_t hdr, geom, off, bpart, box_id, quarter, start, split, hist, bstart, key2, idx2, pay2,
-        tmp, perm, payload, payq, fbar, fsave, partials, scratch64, total;
+        tmp, perm, payload, payq, fbar, fsave, partials, scratch64, chunks, total;
     int64_t max_agents, max_boxes, n_part, nblk_a_max, nb_cap, nblk_b_max;
     int32_t max_sims;
     int32_t dtype;
@@ -146,6 +148,10 @@ constexpr Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_
     L.partials = take(16 * (size_t)L.n_part);
     // int64 scratch for the neighbour-offset scan: one entry per scan tile of n+1 items
     L.scratch64 = take(8 * (size_t)((na + 1 + kScanTile - 1) / kScanTile + 1));
+    // chunk descriptors of oversized buckets (32 bytes each): two consecutive
+    // chunks of a bucket hold more than kSortStage agents, so a bucket has at
+    // most 2 * agents / kSortStage + 1 of them
+    L.chunks = take(32 * (size_t)(2 * (na / kSortStage + 1) + L.nb_cap));
     L.total = o;
     return L;
 }
@@ -178,6 +184,7 @@ struct Dev {
     void* fsave;        // forces of the last forward step that kept them (slot order)
     double* partials;
     long long* scratch64;
+    int4* chunks;       // 2 per descriptor: (bucket, s0, kb, ke), (cs, ce, 0, 0)
 };
 
 inline Dev resolve(const Layout& L, void* base)
@@ -207,6 +214,7 @@ inline Dev resolve(const Layout& L, void* base)
     d.fsave = b + L.fsave;
     d.partials = reinterpret_cast<double*>(b + L.partials);
     d.scratch64 = reinterpret_cast<long long*>(b + L.scratch64);
+    d.chunks = reinterpret_cast<int4*>(b + L.chunks);
     return d;
 }
 

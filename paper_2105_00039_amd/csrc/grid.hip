@@ -440,6 +440,7 @@ __device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t 
         hdr->nb = err ? 0 : (int32_t)nb;
         hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
         hdr->build_gen = hdr->build_gen + 1u;
+        hdr->nchunk = 0u;
         if (!err) start[boxes] = (int32_t)n;
     }
 }
@@ -447,6 +448,8 @@ __device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t 
 // Bounds partials above which a single-simulation build reduces them in a
 // launch of its own (k_geometry1) rather than in every histogram block.
 constexpr int kGeomSplit = 1024;
+// Blocks of the chunk sort of such builds (three per CU).
+constexpr int kSortChunkBlocks = 768;
 
 // Zero the (bucket x tile) count matrix of a large single build, whose
 // histogram then writes only nonzero counts.  Sized by the bucket count the
@@ -889,7 +892,6 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
 // -------------------------------------------------------------- bucket sort
 
 constexpr int kSortBoxes = 1 << kSBMax;
-constexpr int kSortStage = 4096;   // buckets up to this many agents are sorted in LDS
 
 // Quarter counts of one box member, packed as the split word's bytes 0..2
 // (members in quarters below 1, 2, 3).
@@ -957,6 +959,133 @@ __device__ __forceinline__ int sim_of_box(const SimGeom* __restrict__ g, int B, 
 // index) there, and written in slot order; a member's box is the one whose
 // slot range holds its arrival slot.  A single box above kSortStage agents is
 // ranked straight from global memory.
+// The chunk that starts at box kb (first slot cs, relative to the bucket's
+// start): boxes [kb, ke) ending at or before cs + kSortStage, or the single
+// box kb if that alone is larger; ce: its end slot.  c[k]: end of box k.
+__device__ __forceinline__ void chunk_end(const int32_t* c, int nbox, int kb, int cs, int& ke,
+                                          int& ce)
+{
+    int lo = kb, hi = nbox;   // first box ending beyond the limit lies in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (c[mid] - cs > kSortStage) hi = mid; else lo = mid + 1;
+    }
+    ke = lo > kb ? lo : kb + 1;
+    ce = c[ke - 1];
+}
+
+// Sort one chunk (boxes [kb, ke), slots [cs, ce) of the bucket starting at
+// slot s0 and box b0): c[k] (k in [kb - 1, ke)) holds box ends relative to s0.
+template <int M, bool GATHER>
+__device__ void sort_chunk(int s0, int b0, int kb, int ke, int cs, int ce, const int32_t* c,
+                           int32_t* mem, uint8_t* memq, int32_t* inv,
+                           const int32_t* __restrict__ key2, const int32_t* __restrict__ idx2,
+                           const PaySrc<M, GATHER>& src, const int32_t* __restrict__ tmp,
+                           uint32_t* __restrict__ split, int32_t* __restrict__ perm,
+                           typename Mode<M>::Pay* __restrict__ pay, const SlotQ& s32)
+{
+    const int cn = ce - cs;
+    if (cn <= kSortStage) {
+        // each thread's (at most U) members: all loads issued before any use
+        constexpr int U = kSortStage / kSortThreads;
+        static_assert(U * kSortThreads == kSortStage, "whole rounds per chunk");
+        int pm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = threadIdx.x + u * kSortThreads;
+            pm[u] = j < cn ? tmp[s0 + cs + j] : 0;
+        }
+        int32_t id[U], kq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            id[u] = idx2[s0 + pm[u]];
+            kq[u] = key2[s0 + pm[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = threadIdx.x + u * kSortThreads;
+            if (j < cn) {
+                mem[j] = id[u];
+                memq[j] = (uint8_t)(kq[u] & 3);
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < cn; j += kSortThreads) {
+            int k0 = kb, k1 = ke - 1;   // box of arrival slot cs + j: first with c[k] > cs + j
+            while (k0 < k1) {
+                const int mid = (k0 + k1) >> 1;
+                if (c[mid] > cs + j) k1 = mid; else k0 = mid + 1;
+            }
+            const int k = k0, q = memq[j];
+            const int32_t orig = mem[j];
+            const int bs = (k > 0 ? c[k - 1] : 0) - cs, be = c[k] - cs;
+            int r = 0;
+            uint32_t w = 0;
+            for (int m = bs; m < be; ++m) {
+                const int qm = memq[m];
+                r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
+                w += split_inc(qm);
+            }
+            if (r == 0)
+                reinterpret_cast<uint2*>(split)[b0 + k] =
+                    make_uint2((uint32_t)(s0 + cs + bs), split_word(w, be - bs));
+            inv[bs + r] = j;
+        }
+        __syncthreads();
+        // FP64 inputs are written in two halves (fewer 8-byte values in
+        // flight, as in the staged path)
+        constexpr int HALVES = 2;
+        constexpr int UH = U / HALVES;
+#pragma unroll
+        for (int hh = 0; hh < HALVES; ++hh) {
+            int jj[UH], pw[UH];
+#pragma unroll
+            for (int u = 0; u < UH; ++u) {
+                const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
+                jj[u] = p < cn ? inv[p] : 0;
+                pw[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
+            }
+            typename Mode<M>::Pay q[UH];
+            int bx[UH];
+#pragma unroll
+            for (int u = 0; u < UH; ++u) {
+                q[u] = src.get(s0 + pw[u], mem[jj[u]]);
+                bx[u] = b0 + (key2[s0 + pw[u]] >> 2);
+            }
+#pragma unroll
+            for (int u = 0; u < UH; ++u) {
+                const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
+                if (p < cn) {
+                    perm[s0 + cs + p] = mem[jj[u]];
+                    pay[s0 + cs + p] = q[u];
+                    s32.put(s0 + cs + p, q[u], bx[u]);
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        // one box (ke = kb + 1) larger than the stage
+        const int k = kb;
+        for (int j = threadIdx.x; j < cn; j += kSortThreads) {
+            const int pe = tmp[s0 + cs + j];
+            const int q = key2[s0 + pe] & 3;
+            const int32_t orig = idx2[s0 + pe];
+            int r = 0;
+            for (int m = 0; m < cn; ++m) {
+                const int pm = tmp[s0 + cs + m];
+                const int qm = key2[s0 + pm] & 3;
+                r += (qm < q || (qm == q && idx2[s0 + pm] < orig)) ? 1 : 0;
+            }
+            if (r == 0)
+                reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + cs), kSplitNone);
+            perm[s0 + cs + r] = orig;
+            const typename Mode<M>::Pay qv = src.get(s0 + pe, orig);
+            pay[s0 + cs + r] = qv;
+            s32.put(s0 + cs + r, qv, b0 + k);
+        }
+    }
+}
+
 template <int M, bool GATHER>
 __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t* mem, uint8_t* memq,
                             int32_t* inv, const int32_t* __restrict__ key2,
@@ -968,114 +1097,10 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
 {
     int kb = 0, cs = 0;   // first box and first slot of the chunk (block-uniform)
     while (kb < nbox) {
-        // last box of the chunk: boxes [kb, ke) end at or before cs + kSortStage
-        int lo = kb, hi = nbox;   // first box ending beyond the limit lies in [lo, hi]
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (c[mid] - cs > kSortStage) hi = mid; else lo = mid + 1;
-        }
-        const int ke = lo > kb ? lo : kb + 1;
-        const int ce = c[ke - 1];
-        const int cn = ce - cs;
-        if (cn <= kSortStage) {
-            // each thread's (at most U) members: all loads issued before any use
-            constexpr int U = kSortStage / kSortThreads;
-            static_assert(U * kSortThreads == kSortStage, "whole rounds per chunk");
-            int pm[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = threadIdx.x + u * kSortThreads;
-                pm[u] = j < cn ? tmp[s0 + cs + j] : 0;
-            }
-            int32_t id[U], kq[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                id[u] = idx2[s0 + pm[u]];
-                kq[u] = key2[s0 + pm[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int j = threadIdx.x + u * kSortThreads;
-                if (j < cn) {
-                    mem[j] = id[u];
-                    memq[j] = (uint8_t)(kq[u] & 3);
-                }
-            }
-            __syncthreads();
-            for (int j = threadIdx.x; j < cn; j += kSortThreads) {
-                int k0 = kb, k1 = ke - 1;   // box of arrival slot cs + j: first with c[k] > cs + j
-                while (k0 < k1) {
-                    const int mid = (k0 + k1) >> 1;
-                    if (c[mid] > cs + j) k1 = mid; else k0 = mid + 1;
-                }
-                const int k = k0, q = memq[j];
-                const int32_t orig = mem[j];
-                const int bs = (k > 0 ? c[k - 1] : 0) - cs, be = c[k] - cs;
-                int r = 0;
-                uint32_t w = 0;
-                for (int m = bs; m < be; ++m) {
-                    const int qm = memq[m];
-                    r += (qm < q || (qm == q && mem[m] < orig)) ? 1 : 0;
-                    w += split_inc(qm);
-                }
-                if (r == 0)
-                    reinterpret_cast<uint2*>(split)[b0 + k] =
-                        make_uint2((uint32_t)(s0 + cs + bs), split_word(w, be - bs));
-                inv[bs + r] = j;
-            }
-            __syncthreads();
-            // FP64 inputs are written in two halves (fewer 8-byte values in
-            // flight, as in the staged path)
-            constexpr int HALVES = 2;
-            constexpr int UH = U / HALVES;
-#pragma unroll
-            for (int hh = 0; hh < HALVES; ++hh) {
-                int jj[UH], pw[UH];
-#pragma unroll
-                for (int u = 0; u < UH; ++u) {
-                    const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
-                    jj[u] = p < cn ? inv[p] : 0;
-                    pw[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
-                }
-                typename Mode<M>::Pay q[UH];
-                int bx[UH];
-#pragma unroll
-                for (int u = 0; u < UH; ++u) {
-                    q[u] = src.get(s0 + pw[u], mem[jj[u]]);
-                    bx[u] = b0 + (key2[s0 + pw[u]] >> 2);
-                }
-#pragma unroll
-                for (int u = 0; u < UH; ++u) {
-                    const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
-                    if (p < cn) {
-                        perm[s0 + cs + p] = mem[jj[u]];
-                        pay[s0 + cs + p] = q[u];
-                        s32.put(s0 + cs + p, q[u], bx[u]);
-                    }
-                }
-            }
-            __syncthreads();
-        } else {
-            // one box (ke = kb + 1) larger than the stage
-            const int k = kb;
-            for (int j = threadIdx.x; j < cn; j += kSortThreads) {
-                const int pe = tmp[s0 + cs + j];
-                const int q = key2[s0 + pe] & 3;
-                const int32_t orig = idx2[s0 + pe];
-                int r = 0;
-                for (int m = 0; m < cn; ++m) {
-                    const int pm = tmp[s0 + cs + m];
-                    const int qm = key2[s0 + pm] & 3;
-                    r += (qm < q || (qm == q && idx2[s0 + pm] < orig)) ? 1 : 0;
-                }
-                if (r == 0)
-                    reinterpret_cast<uint2*>(split)[b0 + k] = make_uint2((uint32_t)(s0 + cs), kSplitNone);
-                perm[s0 + cs + r] = orig;
-                const typename Mode<M>::Pay qv = src.get(s0 + pe, orig);
-                pay[s0 + cs + r] = qv;
-                s32.put(s0 + cs + r, qv, b0 + k);
-            }
-        }
+        int ke, ce;
+        chunk_end(c, nbox, kb, cs, ke, ce);
+        sort_chunk<M, GATHER>(s0, b0, kb, ke, cs, ce, c, mem, memq, inv, key2, idx2, src, tmp,
+                              split, perm, pay, s32);
         kb = ke;
         cs = ce;
     }
@@ -1085,10 +1110,14 @@ __device__ void sort_chunks(int s0, int nbox, int b0, const int32_t* c, int32_t*
 // two halves so that no mode needs more): three 512-thread blocks then fit a
 // CU, so the 2M-agent build's ~740 buckets run in one round instead of ~1.4
 // (bucket sort 42.8 -> 33.9 us on the sorted state).
-template <int M, bool GATHER>
+// DEFER (large single builds): a bucket above the LDS stage does its counts,
+// box starts and arrival slots here, then hands its chunks to k_sort_chunks
+// (descriptors in `chunks`, capacity `cap`), so the chunks of the densest
+// buckets are sorted by many blocks at once instead of one after another.
+template <int M, bool GATHER, bool DEFER>
 __global__ __launch_bounds__(kSortThreads)
 __attribute__((amdgpu_waves_per_eu(6)))
-void k_bucketsort(const Header* __restrict__ hdr,
+void k_bucketsort(Header* __restrict__ hdr,
                                                              const int32_t* __restrict__ key2,
                                                              const int32_t* __restrict__ idx2,
                                                              const typename Mode<M>::Pay* __restrict__ pay2,
@@ -1104,7 +1133,8 @@ void k_bucketsort(const Header* __restrict__ hdr,
                                                              typename Mode<M>::Pay* __restrict__ pay,
                                                              uint2* __restrict__ payq,
                                                              const SimGeom* __restrict__ geom,
-                                                             int32_t B)
+                                                             int32_t B, int4* __restrict__ chunks,
+                                                             int32_t cap)
 {
     __shared__ int32_t c[kSortBoxes];
     __shared__ int s_sims[2];
@@ -1200,8 +1230,34 @@ void k_bucketsort(const Header* __restrict__ hdr,
     }
     __syncthreads();
     if (!staged) {   // block-uniform
-        sort_chunks<M, GATHER>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, src, tmp, split, perm, pay,
-                       SlotQ(payq, geom, s_sims[0], s_sims[1]));
+        if constexpr (DEFER) {
+            if (threadIdx.x == 0) {
+                int cnt = 0;
+                for (int kb = 0, cs = 0; kb < nbox; ++cnt) {
+                    int ke, ce;
+                    chunk_end(c, nbox, kb, cs, ke, ce);
+                    kb = ke;
+                    cs = ce;
+                }
+                const int base = (int)atomicAdd(&hdr->nchunk, (uint32_t)cnt);
+                if (base + cnt > cap) {
+                    atomicOr(&hdr->error, (uint32_t)ERR_CAPACITY);   // not reached: cap bounds it
+                } else {
+                    int i = base;
+                    for (int kb = 0, cs = 0; kb < nbox; ++i) {
+                        int ke, ce;
+                        chunk_end(c, nbox, kb, cs, ke, ce);
+                        chunks[2 * i] = make_int4(b, s0, kb, ke);
+                        chunks[2 * i + 1] = make_int4(cs, ce, 0, 0);
+                        kb = ke;
+                        cs = ce;
+                    }
+                }
+            }
+        } else {
+            sort_chunks<M, GATHER>(s0, nbox, b0, c, mem, memq, inv, key2, idx2, src, tmp, split,
+                                   perm, pay, SlotQ(payq, geom, s_sims[0], s_sims[1]));
+        }
         return;
     }
     // 4. c[k] now holds the end of box k.  Rank among box mates by (quarter,
@@ -1264,6 +1320,47 @@ void k_bucketsort(const Header* __restrict__ hdr,
     }
 }
 
+// The chunks handed over by a DEFER bucket sort (single simulation): each
+// block takes descriptors i = blockIdx.x, + gridDim.x, ..., loads the
+// chunk's box ends from the box starts and sorts it as the bucket sort would.
+template <int M, bool GATHER>
+__global__ __launch_bounds__(kSortThreads)
+__attribute__((amdgpu_waves_per_eu(6)))
+void k_sort_chunks(const Header* __restrict__ hdr, const int4* __restrict__ chunks, int32_t cap,
+                   const int32_t* __restrict__ key2, const int32_t* __restrict__ idx2,
+                   const typename Mode<M>::Pay* __restrict__ pay2,
+                   const typename Mode<M>::In* __restrict__ x,
+                   const typename Mode<M>::In* __restrict__ y,
+                   const typename Mode<M>::In* __restrict__ z,
+                   const typename Mode<M>::In* __restrict__ d,
+                   const int32_t* __restrict__ start, uint32_t* __restrict__ split,
+                   const int32_t* __restrict__ tmp, int32_t* __restrict__ perm,
+                   typename Mode<M>::Pay* __restrict__ pay, uint2* __restrict__ payq,
+                   const SimGeom* __restrict__ geom)
+{
+    __shared__ int32_t c[kSortBoxes];
+    __shared__ int32_t mem[kSortStage];
+    __shared__ uint8_t memq[kSortStage];
+    __shared__ int32_t inv[kSortStage];
+    if (hdr->error) return;
+    const int nc = (int)hdr->nchunk < cap ? (int)hdr->nchunk : cap;
+    const int sb = hdr->sb;
+    const PaySrc<M, GATHER> src{pay2, x, y, z, d};
+    const SlotQ s32(payq, geom, 0, 0);
+    for (int i = blockIdx.x; i < nc; i += gridDim.x) {   // block-uniform
+        const int4 d0 = chunks[2 * i], d1 = chunks[2 * i + 1];
+        const int s0 = d0.y, kb = d0.z, ke = d0.w, cs = d1.x, ce = d1.y;
+        const int b0 = d0.x << sb;
+        // box ends relative to the bucket start, boxes kb - 1 .. ke - 1
+        for (int k = kb - 1 + (int)threadIdx.x; k < ke; k += kSortThreads)
+            if (k >= 0) c[k] = start[b0 + k + 1] - s0;
+        __syncthreads();
+        sort_chunk<M, GATHER>(s0, b0, kb, ke, cs, ce, c, mem, memq, inv, key2, idx2, src, tmp,
+                              split, perm, pay, s32);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------- canonical order
 
 // The canonical order of the exports (ascending box, then input index) from
@@ -1305,10 +1402,22 @@ void sort_passes(const Layout& L, const Dev& D, const typename Mode<M>::In* x,
         k_partition<M, GATHER><<<nba, kTileThreads, 0, s>>>(x, y, z, d, n, D.hdr, D.box_id,
                                                             D.quarter, D.hist, btot, D.key2, D.idx2,
                                                             static_cast<Pay*>(D.pay2));
-    k_bucketsort<M, GATHER><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
-        D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
-        D.split, D.tmp, D.perm, static_cast<Pay*>(D.payload), D.payq,
-        static_cast<const SimGeom*>(D.geom), B);
+    const int32_t cap = (int32_t)(2 * (L.max_agents / kSortStage + 1) + L.nb_cap);
+    if (B == 1 && n > (int64_t)kGeomSplit * kBoundsChunk) {
+        k_bucketsort<M, GATHER, true><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
+            D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
+            D.split, D.tmp, D.perm, static_cast<Pay*>(D.payload), D.payq,
+            static_cast<const SimGeom*>(D.geom), B, D.chunks, cap);
+        k_sort_chunks<M, GATHER><<<kSortChunkBlocks, kSortThreads, 0, s>>>(
+            D.hdr, D.chunks, cap, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d,
+            D.start, D.split, D.tmp, D.perm, static_cast<Pay*>(D.payload), D.payq,
+            static_cast<const SimGeom*>(D.geom));
+    } else {
+        k_bucketsort<M, GATHER, false><<<(unsigned)L.nb_cap, kSortThreads, 0, s>>>(
+            D.hdr, D.key2, D.idx2, static_cast<const Pay*>(D.pay2), x, y, z, d, btot, D.start,
+            D.split, D.tmp, D.perm, static_cast<Pay*>(D.payload), D.payq,
+            static_cast<const SimGeom*>(D.geom), B, D.chunks, cap);
+    }
 }
 
 template <int M>
