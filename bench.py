@@ -216,7 +216,7 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     return total, force_ms, ws, t
 
 
-def time_rollout_grad(ms, torch, dtype, steps=50, ckpt=10, reps=2, seed=0):
+def time_rollout_grad(ms, torch, dtype, steps=50, ckpt=10, reps=5, seed=0):
     """The differentiation workload: 262,144 agents at ~12 neighbours, a
     `steps`-step rollout with checkpoints every `ckpt` steps, loss = mean
     squared distance of the final positions to seeded targets, gradients with
@@ -243,19 +243,26 @@ def time_rollout_grad(ms, torch, dtype, steps=50, ckpt=10, reps=2, seed=0):
 
     once()
     torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
+    # each rollout timed on its own and the median reported: the eager
+    # rollout issues ~1,000 launches from the host, and a stall of the host
+    # thread now and then doubles one rollout's time
+    times = []
     for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
         once()
-    b.record()
-    torch.cuda.synchronize()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
     ms.device_status(ws)
-    sec = a.elapsed_time(b) / 1e3 / reps
+    sec = float(np.median(times))
     return dict(value=pop.n * steps / sec, unit="agent-steps/s", ms_per_rollout=sec * 1e3,
+                ms_per_rollout_min_max=[min(times) * 1e3, max(times) * 1e3], reps=reps,
                 n_agents=pop.n, steps=steps, ckpt_every=ckpt, dtype=dtype,
                 what="forward rollout + backward (recompute from checkpoints, accumulating "
-                     "backward steps) per agent-step of the rollout; eager, events around both")
+                     "backward steps) per agent-step of the rollout; eager, events around "
+                     "each rollout, median of the repetitions")
 
 
 def time_host_state(ms, torch, arrs, steps, warmup):
