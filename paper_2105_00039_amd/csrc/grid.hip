@@ -892,6 +892,8 @@ __global__ __launch_bounds__(kTileThreads) void k_partition_lds(const typename M
 // -------------------------------------------------------------- bucket sort
 
 constexpr int kSortBoxes = 1 << kSBMax;
+static_assert(kSortStage <= 4096 && kSortBoxes <= 4096,
+              "the chunk sort packs a box and an arrival slot in 12 bits each");
 
 // Quarter counts of one box member, packed as the split word's bytes 0..2
 // (members in quarters below 1, 2, 3).
@@ -1029,29 +1031,30 @@ __device__ void sort_chunk(int s0, int b0, int kb, int ke, int cs, int ce, const
             if (r == 0)
                 reinterpret_cast<uint2*>(split)[b0 + k] =
                     make_uint2((uint32_t)(s0 + cs + bs), split_word(w, be - bs));
-            inv[bs + r] = j;
+            // final slot -> box within the chunk (bits 12..23), arrival slot
+            inv[bs + r] = ((k - kb) << 12) | j;
         }
         __syncthreads();
         // FP64 inputs are written in two halves (fewer 8-byte values in
-        // flight, as in the staged path)
+        // flight, as in the staged path).  The box and the input index come
+        // from LDS; only the carry mode still reads the member's position.
         constexpr int HALVES = 2;
         constexpr int UH = U / HALVES;
 #pragma unroll
         for (int hh = 0; hh < HALVES; ++hh) {
-            int jj[UH], pw[UH];
+            int jj[UH], pw[UH], bx[UH];
 #pragma unroll
             for (int u = 0; u < UH; ++u) {
                 const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
-                jj[u] = p < cn ? inv[p] : 0;
-                pw[u] = p < cn ? tmp[s0 + cs + jj[u]] : 0;   // padding lanes read slot s0
+                const int v = p < cn ? inv[p] : 0;   // padding lanes use arrival slot 0
+                jj[u] = v & 4095;
+                bx[u] = b0 + kb + (v >> 12);
+                pw[u] = 0;
+                if constexpr (!GATHER) pw[u] = tmp[s0 + cs + jj[u]];
             }
             typename Mode<M>::Pay q[UH];
-            int bx[UH];
 #pragma unroll
-            for (int u = 0; u < UH; ++u) {
-                q[u] = src.get(s0 + pw[u], mem[jj[u]]);
-                bx[u] = b0 + (key2[s0 + pw[u]] >> 2);
-            }
+            for (int u = 0; u < UH; ++u) q[u] = src.get(s0 + pw[u], mem[jj[u]]);
 #pragma unroll
             for (int u = 0; u < UH; ++u) {
                 const int p = threadIdx.x + (hh * UH + u) * kSortThreads;
