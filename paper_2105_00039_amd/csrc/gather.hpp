@@ -136,6 +136,29 @@ __device__ __forceinline__ void contact_force(const F4& pi, const F4& q, float k
     }
 }
 
+// 1/x and 1/sqrt(x) for x > 0 from the hardware estimates, each refined by
+// two Newton steps (the error squares at every step), to within about one
+// unit in the last place: the FP64 pair term is held to 1e-12 of its scale,
+// not to correct rounding.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    return y;
+}
+
+// FP64: the contact decision and delta from the correctly rounded |u| (so
+// a touching pair gets exactly nothing, as in the oracle), the rest of the
+// term from refined reciprocals: 1/l, 1/(r_i + r_j) and sqrt(rho delta).
 __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double kap, double gam,
                                               double& ax, double& ay, double& az)
 {
@@ -145,9 +168,10 @@ __device__ __forceinline__ void contact_force(const D4& pi, const D4& q, double 
     const double l = sqrt(l2);
     const double delta = rs - l;
     if (delta > 0.0 && l2 > 0.0) {
-        const double rho = pi.w * q.w / rs;
-        const double sv = fmad(kap, delta, -gam * sqrt(rho * delta));
-        const double sl = sv / l;
+        const double rho = pi.w * q.w * rcp_nr(rs);
+        const double rd = rho * delta;
+        const double sv = fmad(kap, delta, -gam * (rd * rsq_nr(rd)));
+        const double sl = sv * rcp_nr(l);
         ax += sl * ux;
         ay += sl * uy;
         az += sl * uz;
