@@ -229,14 +229,19 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
                 h = 0.5f * irq;
                 wj = q.w * ircs;
             } else {
-                const Real l = fsqrt(l2);
+                // the forward's FP64 contact decision (correctly rounded |u|)
+                // and its refined reciprocals
+                const double l = sqrt(l2);
                 delta = rs - l;
-                if (!(delta > (Real)0) || !(l2 > (Real)0)) return;
-                il = (Real)1 / l;
-                rho = pi.w * q.w / rs;
-                sq = fsqrt(rho * delta);
-                h = (Real)0.5 / sq;
-                wj = q.w / rs;
+                if (!(delta > 0.0) || !(l2 > 0.0)) return;
+                il = rcp_nr(l);
+                const double ircs = rcp_nr(rs);
+                rho = pi.w * q.w * ircs;
+                const double rd = rho * delta;
+                const double irq = rsq_nr(rd);
+                sq = rd * irq;
+                h = 0.5 * irq;
+                wj = q.w * ircs;
             }
             const Real ex = ux * il, ey = uy * il, ez = uz * il;
             const Real sv = kap * delta - gam * sq;
