@@ -73,7 +73,14 @@ def workload_stats(ms, ws, n):
     info = g["info"][0]
     nx, ny, nz = info["dims"]
     start = g["start"].cpu().numpy().astype(np.int64)
-    cnt = np.diff(start).reshape(nz, ny, nx)
+    cnt = np.diff(start)
+    ts = int(info["tile_shift"])
+    if ts:   # tiled x-rows (ms_box_order): gather the rows back into (iz, iy) order
+        t = 1 << ts
+        iz, iy = np.meshgrid(np.arange(nz), np.arange(ny), indexing="ij")
+        row = ((iz // t) * (-(-ny // t)) + iy // t) * t * t + (iz % t) * t + iy % t
+        cnt = cnt.reshape(-1, nx)[row]
+    cnt = cnt.reshape(nz, ny, nx)
     pad = np.pad(cnt, 1)
     box27 = np.zeros_like(cnt)
     for dz in range(3):

@@ -81,6 +81,30 @@ typedef enum {
     MS_F32_POS64 = 2
 } ms_dtype;
 
+/* Numbering of a single simulation's boxes (Section IV-A fixes the grid, not
+ * the order of its boxes).  Boxes are always numbered x fastest, box =
+ * ix + nx * row, so the three boxes of every stencil row stay contiguous; the
+ * x-rows (iy, iz) are numbered
+ *   row-major:  row = iz * ny + iy                       (tile_shift 0), or
+ *   tiled:      16 x 16 tiles of (iy, iz), the tiles row-major with
+ *               ty = ceil(ny / 16) tiles along y, rows row-major inside a
+ *               tile: row = ((iz/16) * ty + iy/16) * 256 + (iz%16) * 16
+ *               + iy%16                                (tile_shift 4),
+ *               which adds empty boxes where ny or nz is not a multiple of 16.
+ * Tiles keep the rows an agent reads close together in the box-sorted
+ * order, which saves HBM traffic once a z-plane holds more agents than the
+ * L2 keeps for three planes.  The order changes box ids, box starts, the
+ * slot order and speed; forces and displacements are the same either way.
+ * Batched builds always number rows row-major. */
+typedef enum {
+    MS_BOX_ORDER_AUTO = 0,   /* tiled from 49,152 agents per z-plane when the
+                                tiles add at most 25% boxes and fit the
+                                workspace, row-major otherwise */
+    MS_BOX_ORDER_ROWS = 1,
+    MS_BOX_ORDER_TILES = 2   /* MS_ECAPACITY (device) if the padded box count
+                                exceeds max_boxes */
+} ms_box_order;
+
 /* Force and displacement parameters (Section III, Eq. 1 and the text after it).
  *   kappa      repulsion coefficient
  *   gamma      attraction (adhesion) coefficient
@@ -97,15 +121,18 @@ typedef struct {
     double  edge;       /* box edge = interaction radius */
     int32_t dims[3];    /* boxes per axis: floor((max - min)/edge) + 1 */
     int32_t error;      /* device error bits of the build (0 = fine) */
-    int64_t n_boxes;    /* dims[0]*dims[1]*dims[2] */
+    int64_t n_boxes;    /* dims[0]*dims[1]*dims[2] for row-major rows; with
+                           tiled rows dims[0] * (1 + the largest row number) */
     int64_t box_base;   /* first global box index of this simulation */
     int64_t n_agents;   /* agents of this simulation */
+    int32_t tile_shift; /* 0: row-major rows; 4: 16 x 16 tiled rows (ms_box_order) */
+    int32_t reserved;
 } ms_grid_info;
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
  * fields from n_agents to built are updated by the grid builds.  Treat them as
- * read-only; keep_forces, gather_list, gather_block and sorted_input are the
- * caller's to set. */
+ * read-only; keep_forces, gather_list, gather_block, sorted_input and
+ * box_order are the caller's to set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -143,6 +170,10 @@ typedef struct {
                             its partition.  Only the speed depends on it: the
                             build is the same for any input, and the caller
                             may set or clear it. */
+    int32_t box_order;    /* ms_box_order of the single-simulation builds: 0
+                            (set by ms_workspace_init; auto), 1 row-major or 2
+                            tiled rows (anything else: MS_EINVAL from the
+                            builds).  Batched builds ignore it. */
 } ms_workspace;
 
 /* Bytes of device memory a workspace with these capacities needs (0 for

@@ -71,7 +71,7 @@ class Workspace:
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
                  dtype: str = "f32", device=None, keep_forces: bool = False,
-                 gather_list: int = 0, gather_block: int = 0):
+                 gather_list: int = 0, gather_block: int = 0, box_order: str = "auto"):
         self.lib = _lib.load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -91,6 +91,7 @@ class Workspace:
         self.keep_forces = keep_forces
         self.gather_list = gather_list
         self.gather_block = gather_block
+        self.box_order = box_order
         self.builds = 0   # grid builds issued on this workspace (the autograd layer checks it)
 
     @property
@@ -122,6 +123,23 @@ class Workspace:
     @sorted_input.setter
     def sorted_input(self, on: bool):
         self.c.sorted_input = 1 if on else 0
+
+    _BOX_ORDERS = {"auto": 0, "rows": 1, "tiles": 2}
+
+    @property
+    def box_order(self) -> str:
+        """Row order of the boxes of the single-simulation builds: "auto"
+        (default; 16 x 16 tiles of rows once a z-plane holds many agents),
+        "rows" (row-major) or "tiles".  Box ids, box starts and the slot
+        order follow it; forces and displacements do not."""
+        return {v: k for k, v in self._BOX_ORDERS.items()}.get(int(self.c.box_order),
+                                                               str(self.c.box_order))
+
+    @box_order.setter
+    def box_order(self, v: str):
+        if v not in self._BOX_ORDERS:
+            raise ValueError(f"box_order must be one of {sorted(self._BOX_ORDERS)}, not {v!r}")
+        self.c.box_order = self._BOX_ORDERS[v]
 
     @property
     def keep_forces(self) -> bool:
@@ -388,12 +406,14 @@ def reorder(ws: Workspace, src, out=None):
 
 def grid_info(ws: Workspace):
     """Synchronising per-simulation geometry of the last build (origin, edge,
-    dims, box count, box base, agent count), without copying any array."""
+    dims, box count, box base, agent count, row tile shift), without copying
+    any array."""
     B = max(ws.n_sims, 1)
     info = (_lib.ms_grid_info * B)()
     st = ws.lib.ms_grid_get(ctypes.byref(ws.c), info, None, None, None, _stream(ws.device))
     geo = [dict(origin=tuple(i.origin), edge=i.edge, dims=tuple(i.dims), error=i.error,
-                n_boxes=i.n_boxes, box_base=i.box_base, n_agents=i.n_agents) for i in info]
+                n_boxes=i.n_boxes, box_base=i.box_base, n_agents=i.n_agents,
+                tile_shift=i.tile_shift) for i in info]
     _lib.check(st)
     return geo
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmechstep
 
 MS_OK, MS_EINVAL, MS_ECAPACITY, MS_EDEVICE, MS_EINPUT = 0, 1, 2, 3, 4
 MS_F32, MS_F64, MS_F32_POS64 = 0, 1, 2
+MS_BOX_ORDER_AUTO, MS_BOX_ORDER_ROWS, MS_BOX_ORDER_TILES = 0, 1, 2
 STATUS_NAMES = {0: "MS_OK", 1: "MS_EINVAL", 2: "MS_ECAPACITY", 3: "MS_EDEVICE", 4: "MS_EINPUT"}
 
 EXPORTS = (
@@ -40,7 +41,8 @@ class ms_grid_info(ctypes.Structure):
     _fields_ = [("origin", ctypes.c_double * 3), ("edge", ctypes.c_double),
                 ("dims", ctypes.c_int32 * 3), ("error", ctypes.c_int32),
                 ("n_boxes", ctypes.c_int64), ("box_base", ctypes.c_int64),
-                ("n_agents", ctypes.c_int64)]
+                ("n_agents", ctypes.c_int64), ("tile_shift", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ms_workspace(ctypes.Structure):
@@ -50,7 +52,7 @@ class ms_workspace(ctypes.Structure):
                 ("n_agents", ctypes.c_int64), ("n_sims", ctypes.c_int32),
                 ("built", ctypes.c_int32), ("keep_forces", ctypes.c_int32),
                 ("gather_list", ctypes.c_int32), ("gather_block", ctypes.c_int32),
-                ("sorted_input", ctypes.c_int32)]
+                ("sorted_input", ctypes.c_int32), ("box_order", ctypes.c_int32)]
 
 
 class MechStepError(RuntimeError):

@@ -119,6 +119,7 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->gather_list = 0;
     ws->sorted_input = 0;
     ws->gather_block = 0;
+    ws->box_order = MS_BOX_ORDER_AUTO;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -134,6 +135,8 @@ static ms_status build_common(ms_workspace* ws, const void* x, const void* y, co
     if (B > ws->max_sims) return fail(MS_ECAPACITY, "%s: %d simulations exceed max_sims = %d", who, B,
                                       ws->max_sims);
     if (!std::isfinite(edge)) return fail(MS_EINVAL, "%s: non-finite edge", who);
+    if (ws->box_order < MS_BOX_ORDER_AUTO || ws->box_order > MS_BOX_ORDER_TILES)
+        return fail(MS_EINVAL, "%s: box_order = %d is not an ms_box_order", who, ws->box_order);
     if (n > 0) {
         st = check_arrays(who, in_size(ws->dtype), {x, y, z, d});
         if (st) return st;
@@ -148,7 +151,7 @@ static ms_status build_common(ms_workspace* ws, const void* x, const void* y, co
     if (n == 0) return ok();
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_grid_build(L, ms::resolve(L, ws->base), x, y, z, d, n, off, B, edge,
-                                           edges, sorted_input, as_stream(stream)),
+                                           edges, sorted_input, ws->box_order, as_stream(stream)),
                      who);
 }
 
@@ -483,6 +486,8 @@ ms_status ms_grid_get(const ms_workspace* ws, ms_grid_info* info, int32_t* box_i
             I.n_boxes = g[b].n_boxes;
             I.box_base = g[b].box_base;
             I.n_agents = off[b + 1] - off[b];
+            I.tile_shift = g[b].tile_shift;
+            I.reserved = 0;
         }
     }
     if (h.error) return fail(MS_EINVAL, "%s: the last build failed on the device (error bits %u)", who,
@@ -638,7 +643,8 @@ ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, cons
     // a fresh header for every call: the array keeps the previous call's state
     hipError_t e = ms::launch_init(L, D, s);
     if (e == hipSuccess && n > 0)
-        e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, false, s);
+        e = ms::launch_grid_build(L, D, x, y, z, d, n, nullptr, 1, edge, nullptr, false,
+                                  MS_BOX_ORDER_AUTO, s);
     if (e == hipSuccess && n > 0)
         e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
                              false, ms::kMaxContacts, ms::kBlock, s);

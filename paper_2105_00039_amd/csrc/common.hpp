@@ -25,6 +25,8 @@ constexpr int kSortStage = 4096;      // buckets up to this many agents are sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
 constexpr int kForceBlockSmall = 128; // the smaller block the forward gather may use
+constexpr int kRowTileShift = 4;      // tiled x-rows: 16 x 16 tiles of (iy, iz)
+constexpr int64_t kTilePlaneAgents = 49152;   // agents per z-plane from which a build tiles its rows
 // Quantised slot copy of plain builds (the gather's candidate test): quanta
 // per box edge, and the margin (in quanta) added to the summed radii.
 constexpr int kQuantScale = 8192;
@@ -55,7 +57,7 @@ struct Header {
     int64_t n_agents;
     int64_t need_boxes;    // boxes the last build asked for (even when over capacity)
     uint32_t off_err;      // simulation-offset check of the current build (cleared after use)
-    int32_t total_rows;    // x-rows of boxes over all simulations of the last build
+    int32_t pad0;
     uint32_t build_gen;    // incremented by every build
     uint32_t fwd_gen;      // build_gen of the forward step that kept its forces
     ms_params fwd_params;  // parameters of that forward step
@@ -71,7 +73,7 @@ struct SimGeom {
     int32_t dims[3];
     int32_t error;
     int32_t box_base;
-    int32_t row_base;   // first global x-row (dims[1]*dims[2] rows per simulation)
+    int32_t tile_shift;   // x-row numbering: 0 row-major, kRowTileShift tiled (box_row)
     int64_t n_boxes;
 };
 static_assert(sizeof(SimGeom) == 64, "geom size");
@@ -230,6 +232,18 @@ __device__ __forceinline__ double dec_f64(unsigned long long k)
 {
     unsigned long long u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
     return __longlong_as_double(u);
+}
+
+// Number of the x-row (iy, iz) of a grid with ny rows along y.  Boxes are
+// numbered x fastest (box = ix + nx * row), so the boxes of a row are
+// contiguous whatever the row order.  s = 0: row-major, row = iz*ny + iy.
+// s > 0: the rows are grouped in 2^s x 2^s tiles of (iy, iz), the tiles in
+// row-major order (ceil(ny / 2^s) along y), and the rows row-major inside a
+// tile; the tiles of the last column along y may be partly empty.
+__host__ __device__ __forceinline__ int box_row(int iy, int iz, int ny, int s)
+{
+    const int m = (1 << s) - 1, nty = (ny + m) >> s;
+    return ((((iz >> s) * nty + (iy >> s)) << (2 * s)) + ((iz & m) << s) + (iy & m));
 }
 
 // Box index along one axis: floor((p - o)/e) in FP64, clamped to [0, dim-1].

@@ -75,8 +75,9 @@ __device__ __forceinline__ Cell cell_of(const SimGeom& g, Real x, Real y, Real z
     return c;
 }
 
-// Calls fn(j0, j1) for the 9 runs of the 27-box stencil in ascending box
-// order ((dz, dy) lexicographic; each run ascending in x).
+// Calls fn(j0, j1) for the 9 runs of the 27-box stencil in (dz, dy)
+// lexicographic order (ascending box order for row-major rows), each run
+// ascending in x.
 template <typename Fn>
 __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int32_t* __restrict__ start,
                                              Fn&& fn)
@@ -90,7 +91,7 @@ __device__ __forceinline__ void for_each_run(const SimGeom& g, Cell c, const int
         for (int dy = -1; dy <= 1; ++dy) {
             const int cy = c.iy + dy;
             if (cy < 0 || cy >= ny) continue;
-            const int row = g.box_base + (cz * ny + cy) * nx;
+            const int row = g.box_base + box_row(cy, cz, ny, g.tile_shift) * nx;
             fn(start[row + x0], start[row + x1 + 1]);
         }
     }
@@ -213,7 +214,18 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
     const double dy2[3] = {ly * ly, 0.0, hy * hy};
     const double dz2[3] = {lz * lz, 0.0, hz * hz};
     const float ef = (float)e, c4 = 4.0f / ef, lxf = (float)lx, pad = 1e-5f * ef;
-    const int rowc = g.box_base + (c.iz * ny + c.iy) * nx, plane = nx * ny;
+    // box_row of the 9 rows as the sum of a y part and a z part (the same
+    // terms box_row adds); tile shift 0 gives iz*ny + iy
+    // (unsigned: the rows at -1 wrap and are never used)
+    const uint32_t ts = (uint32_t)g.tile_shift, tm = (1u << ts) - 1u;
+    const uint32_t nty = ((uint32_t)ny + tm) >> ts;
+    uint32_t ry[3], rz[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint32_t cy = (uint32_t)(c.iy + k - 1), cz = (uint32_t)(c.iz + k - 1);
+        ry[k] = ((cy >> ts) << (2u * ts)) + (cy & tm);
+        rz[k] = (((cz >> ts) * nty) << (2u * ts)) + ((cz & tm) << ts);
+    }
     uint32_t i0[9], i1[9];
     int qa[9], qb[9];
     bool okr[9];
@@ -229,7 +241,7 @@ __device__ __forceinline__ Runs stencil_runs(const SimGeom& g, Cell c,
         const float rlo = lxf - w + (lo_prev ? ef : 0.0f);
         const float rhi = lxf + w - (hi_next ? ef : 0.0f);
         const int ta = (int)floorf(rlo * c4), tb = (int)floorf(rhi * c4);
-        const int row = rowc + (r / 3 - 1) * plane + (r % 3 - 1) * nx;
+        const int row = g.box_base + (int)(ry[r % 3] + rz[r / 3]) * nx;
         okr[r] = ok;
         // Byte offsets of the two end boxes (32-bit, from a scalar base).
         // Out-of-range rows read box 0 (an empty run), so all loads are

@@ -364,25 +364,21 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
     __shared__ uint32_t s_err;
     if (threadIdx.x == 0) s_err = 0;
     __syncthreads();
-    long long running = 0, rows = 0;
+    long long running = 0;
     for (int c = 0; c < B; c += 1024) {
         const int s = c + threadIdx.x;
-        long long nb = 0, nr = 0;
+        long long nb = 0;
         if (s < B) {
             nb = geom[s].n_boxes;
-            nr = nb > 0 ? (long long)geom[s].dims[1] * geom[s].dims[2] : 0;
             if (geom[s].error) atomicOr(&s_err, (uint32_t)geom[s].error);
         }
-        long long tot, rtot;
+        long long tot;
         const long long base = block_excl_scan<1024, long long>(nb, s_wave, tot);
-        const long long rbase = block_excl_scan<1024, long long>(nr, s_wave, rtot);
         if (s < B) {
             const long long gb = running + base;
             geom[s].box_base = gb < 2147483647ll ? (int32_t)gb : 0;
-            geom[s].row_base = (int32_t)(rows + rbase);
         }
         running += tot;
-        rows += rtot;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -400,7 +396,6 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
         hdr->n_sims = (uint32_t)B;
         hdr->sb = sb;
         hdr->nb = err ? 0 : (int32_t)nbk;
-        hdr->total_rows = err ? 0 : (int32_t)rows;
         hdr->build_gen = hdr->build_gen + 1u;
         if (!err) start[running] = (int32_t)n;
     }
@@ -408,13 +403,40 @@ __global__ __launch_bounds__(1024) void k_boxbase(Header* hdr, SimGeom* geom, in
 
 // ------------------------------------------------------- bucket histogram
 
-// Single simulation: the build's shape from its geometry g (error word,
-// bucket shift and count) into s_geo / s_shape (shift, bucket count, error);
-// with `write` also the geometry, the build header and start[boxes] = n.
-__device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t nb_cap, bool write,
-                               SimGeom* __restrict__ geom, Header* __restrict__ hdr,
+// Row order of a single simulation's boxes (box_row): row-major, or, for
+// `order` MS_BOX_ORDER_TILES or when MS_BOX_ORDER_AUTO finds many agents per
+// z-plane, 16 x 16 tiles of rows.  An agent reads three z-planes of slots;
+// row-major numbering puts its z-neighbour rows a whole plane of slots away,
+// and once three planes outgrow an XCD's share of the L2 those rows are
+// fetched again from HBM for every plane.  Inside a tile they are 16 rows
+// away.  Auto keeps row-major when the tiles' padding would add more than a
+// quarter to the box count or not fit the workspace.  Sets g.tile_shift and,
+// for tiles, the padded g.n_boxes.
+__device__ void choose_rows(SimGeom& g, int64_t n, int64_t max_boxes, int order)
+{
+    g.tile_shift = 0;
+    if (g.error || g.n_boxes <= 0 || order == MS_BOX_ORDER_ROWS) return;
+    const bool autom = order != MS_BOX_ORDER_TILES;
+    if (autom && n < kTilePlaneAgents * (int64_t)g.dims[2]) return;
+    const int s = kRowTileShift, m = (1 << s) - 1;
+    const long long nty = (g.dims[1] + (long long)m) >> s, lz = g.dims[2] - 1;
+    // 1 + box_row of the last tile's last row, in 64 bits
+    const long long rows = ((((lz >> s) * nty + nty - 1) << (2 * s)) | ((lz & m) << s)) + m + 1;
+    const long long nb = (long long)g.dims[0] * rows;
+    if (autom && (4 * nb > 5 * g.n_boxes || nb > max_boxes)) return;
+    g.tile_shift = s;
+    g.n_boxes = nb;
+}
+
+// Single simulation: the build's shape from its geometry g (row order,
+// error word, bucket shift and count) into s_geo / s_shape (shift, bucket
+// count, error); with `write` also the geometry, the build header and
+// start[boxes] = n.
+__device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t nb_cap, int order,
+                               bool write, SimGeom* __restrict__ geom, Header* __restrict__ hdr,
                                int32_t* __restrict__ start, SimGeom& s_geo, int (&s_shape)[3])
 {
+    choose_rows(g, n, max_boxes, order);
     uint32_t err = (uint32_t)g.error;
     const long long boxes = g.n_boxes;
     if (boxes > max_boxes || boxes >= 2147483647ll) err |= ERR_CAPACITY;
@@ -423,7 +445,6 @@ __device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t 
     bucket_shape(boxes, n, nb_cap, shift, nb);
     if (nb > nb_cap) err |= ERR_CAPACITY;
     g.box_base = 0;
-    g.row_base = 0;
     s_geo = g;
     s_shape[0] = shift;
     s_shape[1] = err ? 0 : (int)nb;
@@ -438,7 +459,6 @@ __device__ void publish_single(SimGeom g, int64_t n, int64_t max_boxes, int64_t 
         hdr->n_sims = 1u;
         hdr->sb = shift;
         hdr->nb = err ? 0 : (int32_t)nb;
-        hdr->total_rows = err ? 0 : g.dims[1] * g.dims[2];
         hdr->build_gen = hdr->build_gen + 1u;
         hdr->nchunk = 0u;
         if (!err) start[boxes] = (int32_t)n;
@@ -474,7 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_clear_hist(const Header* __restrict_
 // histogram block walking the partials with one wavefront.
 __global__ __launch_bounds__(1024) void k_geometry1(const BoundsPart* __restrict__ part,
                                                     int64_t n, double edge, int64_t max_boxes,
-                                                    int64_t nb_cap, SimGeom* __restrict__ geom,
+                                                    int64_t nb_cap, int order,
+                                                    SimGeom* __restrict__ geom,
                                                     Header* __restrict__ hdr,
                                                     int32_t* __restrict__ start)
 {
@@ -527,7 +548,7 @@ __global__ __launch_bounds__(1024) void k_geometry1(const BoundsPart* __restrict
             fl |= s_fl[w];
         }
         const SimGeom g = geometry_from(lo, hi, dm, fl, n > 0, edge);
-        publish_single(g, n, max_boxes, nb_cap, true, geom, hdr, start, s_geo, s_shape);
+        publish_single(g, n, max_boxes, nb_cap, order, true, geom, hdr, start, s_geo, s_shape);
     }
 }
 
@@ -542,7 +563,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                                                  uint8_t* __restrict__ quarter,
                                                  int32_t* __restrict__ hist,
                                                  const BoundsPart* __restrict__ part, double edge,
-                                                 int64_t max_boxes, int64_t nb_cap,
+                                                 int64_t max_boxes, int64_t nb_cap, int order,
                                                  int32_t* __restrict__ start)
 {
     using Real = typename Mode<M>::Real;
@@ -571,8 +592,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
         } else if (threadIdx.x < kWave) {
             const SimGeom g = geometry_of(part, 0, n, 0, edge);
             if (threadIdx.x == 0)
-                publish_single(g, n, max_boxes, nb_cap, blockIdx.x == 0, geom, hdr, start, s_geo,
-                               s_shape);
+                publish_single(g, n, max_boxes, nb_cap, order, blockIdx.x == 0, geom, hdr, start,
+                               s_geo, s_shape);
         }
         __syncthreads();
         if (s_shape[2]) return;   // block-uniform
@@ -595,7 +616,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
         const int ix = axis_index(px, g.origin[0], g.edge, g.dims[0]);
         const int iy = axis_index((double)(Real)y[i], g.origin[1], g.edge, g.dims[1]);
         const int iz = axis_index((double)(Real)z[i], g.origin[2], g.edge, g.dims[2]);
-        const int key = g.box_base + ix + g.dims[0] * (iy + g.dims[1] * iz);
+        const int key = g.box_base + ix + g.dims[0] * box_row(iy, iz, g.dims[1], g.tile_shift);
         box_id[i] = key;
         quarter[i] = (uint8_t)box_quarter(px, g.origin[0], 4.0 / g.edge, g.edge, ix);
         atomicAdd(&h[key >> sb], 1);
@@ -1427,7 +1448,7 @@ template <int M>
 hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const void* yv,
                            const void* zv, const void* dv, int64_t n, const int64_t* off,
                            int32_t B, double edge, const double* edges, bool sorted_input,
-                           hipStream_t s)
+                           int order, hipStream_t s)
 {
     using In = typename Mode<M>::In;
     const In* x = static_cast<const In*>(xv);
@@ -1455,18 +1476,20 @@ hipError_t grid_build_mode(const Layout& L, const Dev& D, const void* xv, const 
     if (batched)
         k_hist<M, true, false><<<nba, kTileThreads, 0, s>>>(x, y, z, n, woff, B, D.geom, D.hdr, D.box_id,
                                                      D.quarter, D.hist, D.bpart, edge, L.max_boxes,
-                                                     L.nb_cap, D.start);
+                                                     L.nb_cap, MS_BOX_ORDER_ROWS, D.start);
     else if (nbb > (unsigned)kGeomSplit) {
-        k_geometry1<<<1, 1024, 0, s>>>(D.bpart, n, edge, L.max_boxes, L.nb_cap, D.geom, D.hdr,
-                                       D.start);
+        k_geometry1<<<1, 1024, 0, s>>>(D.bpart, n, edge, L.max_boxes, L.nb_cap, order, D.geom,
+                                       D.hdr, D.start);
         k_clear_hist<<<1024, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba);
         k_hist<M, false, true><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr,
                                                             D.box_id, D.quarter, D.hist, D.bpart,
-                                                            edge, L.max_boxes, L.nb_cap, D.start);
+                                                            edge, L.max_boxes, L.nb_cap, order,
+                                                            D.start);
     } else
         k_hist<M, false, false><<<nba, kTileThreads, 0, s>>>(x, y, z, n, nullptr, 1, D.geom, D.hdr,
                                                              D.box_id, D.quarter, D.hist, D.bpart,
-                                                             edge, L.max_boxes, L.nb_cap, D.start);
+                                                             edge, L.max_boxes, L.nb_cap, order,
+                                                             D.start);
     int32_t* btot = D.bstart + L.nb_cap + 1;
     k_rowscan<<<(unsigned)L.nb_cap, kBlock, 0, s>>>(D.hdr, D.hist, (int32_t)nba, btot);
     if (sorted_input)
@@ -1503,16 +1526,18 @@ hipError_t launch_canon(const Layout& L, const Dev& D, int64_t n, hipStream_t s)
 hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const void* y,
                              const void* z, const void* d, int64_t n, const int64_t* off,
                              int32_t B, double edge, const double* edges, bool sorted_input,
-                             hipStream_t s)
+                             int order, hipStream_t s)
 {
     switch (L.dtype) {
     case MS_F32:
-        return grid_build_mode<MS_F32>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input, s);
+        return grid_build_mode<MS_F32>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input,
+                                       order, s);
     case MS_F64:
-        return grid_build_mode<MS_F64>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input, s);
+        return grid_build_mode<MS_F64>(L, D, x, y, z, d, n, off, B, edge, edges, sorted_input,
+                                       order, s);
     case MS_F32_POS64:
         return grid_build_mode<MS_F32_POS64>(L, D, x, y, z, d, n, off, B, edge, edges,
-                                             sorted_input, s);
+                                             sorted_input, order, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -14,11 +14,13 @@ hipError_t launch_error_copy(const Dev& D, int32_t* out, hipStream_t s);
 // Uniform grid: bounds -> geometry -> count -> scan -> scatter -> rank.
 // off == nullptr means one simulation of n agents (B must be 1).
 // sorted_input: the inputs are nearly box-sorted, the sort reads the payload
-// from them (same build, different speed).
+// from them (same build, different speed).  order: an ms_box_order, the row
+// order of a single simulation's boxes (batched builds number rows
+// row-major).
 hipError_t launch_grid_build(const Layout& L, const Dev& D, const void* x, const void* y,
                              const void* z, const void* d, int64_t n, const int64_t* off,
                              int32_t B, double edge, const double* edges, bool sorted_input,
-                             hipStream_t s);
+                             int order, hipStream_t s);
 
 // Canonical order of the last build (ascending box, then input index) into
 // D.canon / D.cslot, for the exports.

@@ -59,3 +59,51 @@ def check_gradients(gp, gd, gkg, arrs_o, params, gD, mode, what, edge=0.0):
     nz = Sp > 0
     assert np.all(np.asarray(gp)[~nz] == 0), f"{what}: agents without contacts must get 0"
     return max(w1, w2)
+
+
+def tiled_boxes(box, dims, shift):
+    """Box ids in the exported numbering from the oracle's row-major ids
+    (ix + nx*(iy + ny*iz)): x stays fastest and the x-rows (iy, iz) go to
+    2^shift x 2^shift tiles, tiles row-major with ceil(ny / 2^shift) along y
+    and rows row-major inside a tile (the library's ms_box_order).  Also
+    returns the box count of that numbering."""
+    box = np.asarray(box, dtype=np.int64)
+    nx, ny, nz = (int(v) for v in dims)
+    if shift == 0:
+        return box, nx * ny * nz
+    t = 1 << shift
+    ty = -(-ny // t)
+
+    def row(iy, iz):
+        return ((iz // t) * ty + iy // t) * t * t + (iz % t) * t + iy % t
+
+    ix, r = box % nx, box // nx
+    iy, iz = r % ny, r // ny
+    return ix + nx * row(iy, iz), nx * (int(row(ty * t - 1, nz - 1)) + 1)
+
+
+def grid_in_order(box, dims, shift):
+    """The oracle's grid (row-major box ids) renumbered to the exported
+    order: box ids, box starts (exclusive scan of the per-box counts, n_boxes
+    + 1 entries) and the canonical order (ascending box, then ascending agent
+    index), plus the box count."""
+    key, nb = tiled_boxes(box, dims, shift)
+    cnt = np.bincount(key, minlength=nb) if key.size else np.zeros(nb, dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    perm = np.argsort(key, kind="stable")
+    return key, start, perm, nb
+
+
+def expect_grid(g, box, start, perm, dims, nb, sim=0):
+    """The exported grid g (ms.grid_get) equals the oracle's (box ids, box
+    starts, canonical order, box count nb), renumbered to the row order the
+    build reports (tile_shift)."""
+    info = g["info"][sim]
+    shift = int(info["tile_shift"])
+    if shift:
+        box, start, perm, nb = grid_in_order(box, dims, shift)
+    assert info["n_boxes"] == nb, (info["n_boxes"], nb, shift)
+    assert np.array_equal(g["box_id"].cpu().numpy(), box)
+    assert np.array_equal(g["start"].cpu().numpy(), start)
+    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    return shift

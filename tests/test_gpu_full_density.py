@@ -12,7 +12,7 @@ import torch
 import oracle
 import paper_2105_00039_amd as ms
 from paper_2105_00039_amd import autotune, workloads
-from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+from helpers import NP_IN, UNIT, check_vectors, force_bound, expect_grid, oracle_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -41,10 +41,9 @@ def test_full_size_uniform_2M_density(nbrs, mode):
     ms.device_status(ws)
     g = ms.grid_get(ws)
     o = oracle_inputs(arrs, mode)
+    _, _, dims, nb = oracle.geometry(*o)
     box, start, perm = oracle.grid(*o)
-    assert np.array_equal(g["box_id"].cpu().numpy(), box)
-    assert np.array_equal(g["start"].cpu().numpy(), start)
-    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    expect_grid(g, box, start, perm, dims, nb)
     rng = np.random.default_rng(int(nbrs))
     cnt = np.diff(start.astype(np.int64))
     dense = np.argsort(cnt, kind="stable")[-64:]

@@ -28,7 +28,8 @@ import oracle
 import paper_2105_00039_amd as ms
 from paper_2105_00039_amd import autograd as msa
 from paper_2105_00039_amd import workloads
-from helpers import NP_IN, UNIT, check_gradients, check_vectors, force_bound, oracle_inputs
+from helpers import (NP_IN, UNIT, check_gradients, check_vectors, expect_grid, force_bound,
+                     oracle_inputs)
 
 pytestmark = pytest.mark.gpu
 
@@ -89,10 +90,9 @@ def test_full_size_clusters_16M():
     D = ms.mech_step(ws, P)
     ms.device_status(ws)
     g = ms.grid_get(ws)
+    _, _, dims, nb = oracle.geometry(*o)
     box, start, perm = oracle.grid(*o)
-    assert np.array_equal(g["box_id"].cpu().numpy(), box)
-    assert np.array_equal(g["start"].cpu().numpy(), start)
-    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    expect_grid(g, box, start, perm, dims, nb)
     rng = np.random.default_rng(16)
     cnt = np.diff(start.astype(np.int64))
     dense = np.argsort(cnt, kind="stable")[-64:]

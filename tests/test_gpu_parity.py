@@ -14,7 +14,7 @@ import torch
 import oracle
 import paper_2105_00039_amd as ms
 from paper_2105_00039_amd import workloads
-from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+from helpers import NP_IN, UNIT, check_vectors, force_bound, expect_grid, oracle_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -113,10 +113,7 @@ def test_grid_bit_exact(case, mode):
     assert info["edge"] == edge
     assert tuple(info["dims"]) == tuple(int(v) for v in dims)
     assert np.array_equal(np.array(info["origin"]), origin)
-    assert info["n_boxes"] == nb
-    assert np.array_equal(g["box_id"].cpu().numpy(), box)
-    assert np.array_equal(g["start"].cpu().numpy(), start)
-    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    expect_grid(g, box, start, perm, dims, nb)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -308,10 +305,9 @@ def test_full_size_uniform_2M(mode):
     ms.device_status(ws)
     g = ms.grid_get(ws)
     o = oracle_inputs(arrs, mode)
+    _, _, dims, nb = oracle.geometry(*o)
     box, start, perm = oracle.grid(*o)
-    assert np.array_equal(g["box_id"].cpu().numpy(), box)
-    assert np.array_equal(g["start"].cpu().numpy(), start)
-    assert np.array_equal(g["perm"].cpu().numpy(), perm)
+    expect_grid(g, box, start, perm, dims, nb)
     Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
     _, Do = oracle.step(*o, P)
     S, A, C = oracle.tolerance_scales(*o, 2.0, 1.0, UNIT[mode])

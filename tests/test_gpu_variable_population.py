@@ -10,7 +10,7 @@ import torch
 import oracle
 import paper_2105_00039_amd as ms
 from paper_2105_00039_amd import workloads
-from helpers import NP_IN, UNIT, check_vectors, force_bound, oracle_inputs
+from helpers import NP_IN, UNIT, check_vectors, force_bound, expect_grid, oracle_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -49,10 +49,9 @@ def test_growing_population(mode):
         ms.device_status(ws)
         o = oracle_inputs(arrs, mode)
         g = ms.grid_get(ws)
+        _, _, dims, nb = oracle.geometry(*o)
         box, start, perm = oracle.grid(*o)
-        assert np.array_equal(g["box_id"].cpu().numpy(), box)
-        assert np.array_equal(g["start"].cpu().numpy(), start)
-        assert np.array_equal(g["perm"].cpu().numpy(), perm)
+        expect_grid(g, box, start, perm, dims, nb)
         _, Do = oracle.step(*o, P)
         S, A, _ = oracle.tolerance_scales(*o, P["kappa"], P["gamma"], UNIT[mode])
         Dg = np.stack([a.cpu().numpy().astype(np.float64) for a in D], axis=1)
