@@ -488,38 +488,39 @@ __global__ __launch_bounds__(kBlock) void k_clear_hist(const Header* __restrict_
         hist[i] = 0;
 }
 
-// Single simulation with many bounds partials (more than kGeomSplit): one
-// block of 1,024 threads reduces them all (a few loads per thread, issued
-// together) and publishes geometry and header once, instead of every
-// histogram block walking the partials with one wavefront.
-__global__ __launch_bounds__(1024) void k_geometry1(const BoundsPart* __restrict__ part,
-                                                    int64_t n, double edge, int64_t max_boxes,
-                                                    int64_t nb_cap, int order,
-                                                    SimGeom* __restrict__ geom,
-                                                    Header* __restrict__ hdr,
-                                                    int32_t* __restrict__ start)
+static_assert(kTileThreads == 1024, "block_bounds runs on blocks of 1,024 threads");
+
+// Bounds of a single simulation from its nc partials, reduced by a whole
+// block of 1,024 threads (U partials per thread loaded before any is
+// reduced); valid in thread 0.  Every thread of the block must call it.
+struct BlockBounds {
+    double red[7][1024 / kWave];
+    uint32_t fl[1024 / kWave];
+};
+
+template <int U>
+__device__ void block_bounds(const BoundsPart* __restrict__ part, int64_t nc, BlockBounds& sm,
+                             double (&lo)[3], double (&hi)[3], double& dm, uint32_t& fl)
 {
-    __shared__ double s_red[7][1024 / kWave];
-    __shared__ uint32_t s_fl[1024 / kWave];
-    __shared__ SimGeom s_geo;
-    __shared__ int s_shape[3];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    double lo[3] = {INFINITY, INFINITY, INFINITY};
-    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double dm = -INFINITY;
-    uint32_t fl = 0;
-    const int64_t nc = (n + kBoundsChunk - 1) / kBoundsChunk;
-    constexpr int U = 4;   // partials per thread loaded before any is reduced
+    for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    dm = -INFINITY;
+    fl = 0;
     for (int64_t c0 = threadIdx.x; c0 < nc; c0 += 1024 * U) {
         BoundsPart p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t c = c0 + 1024 * u;
-            if (c < nc) p[u] = part[c];
+            if (c < nc) {
+                p[u] = part[c];
+            } else {
+                for (int k = 0; k < 3; ++k) { p[u].lo[k] = INFINITY; p[u].hi[k] = -INFINITY; }
+                p[u].dmax = -INFINITY;
+                p[u].flags = 0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (c0 + 1024 * u >= nc) break;
             for (int k = 0; k < 3; ++k) {
                 lo[k] = fmin(lo[k], p[u].lo[k]);
                 hi[k] = fmax(hi[k], p[u].hi[k]);
@@ -533,20 +534,40 @@ __global__ __launch_bounds__(1024) void k_geometry1(const BoundsPart* __restrict
     dm = wave_max(dm);
     fl = wave_or(fl);
     if (lane == 0) {
-        for (int k = 0; k < 3; ++k) { s_red[k][wid] = lo[k]; s_red[3 + k][wid] = hi[k]; }
-        s_red[6][wid] = dm;
-        s_fl[wid] = fl;
+        for (int k = 0; k < 3; ++k) { sm.red[k][wid] = lo[k]; sm.red[3 + k][wid] = hi[k]; }
+        sm.red[6][wid] = dm;
+        sm.fl[wid] = fl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < 1024 / kWave; ++w) {
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fmin(lo[k], s_red[k][w]);
-                hi[k] = fmax(hi[k], s_red[3 + k][w]);
-            }
-            dm = fmax(dm, s_red[6][w]);
-            fl |= s_fl[w];
+    if (wid == 0) {
+        // the 16 wave results, one per lane, reduced by wave 0
+        const bool on = lane < 1024 / kWave;
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = wave_min(on ? sm.red[k][lane] : INFINITY);
+            hi[k] = wave_max(on ? sm.red[3 + k][lane] : -INFINITY);
         }
+        dm = wave_max(on ? sm.red[6][lane] : -INFINITY);
+        fl = wave_or(on ? sm.fl[lane] : 0u);
+    }
+}
+
+// Single simulation with many bounds partials (more than kGeomSplit): one
+// block of 1,024 threads reduces them all and publishes geometry and header
+// once, instead of every histogram block reducing them.
+__global__ __launch_bounds__(1024) void k_geometry1(const BoundsPart* __restrict__ part,
+                                                    int64_t n, double edge, int64_t max_boxes,
+                                                    int64_t nb_cap, int order,
+                                                    SimGeom* __restrict__ geom,
+                                                    Header* __restrict__ hdr,
+                                                    int32_t* __restrict__ start)
+{
+    __shared__ BlockBounds s_bb;
+    __shared__ SimGeom s_geo;
+    __shared__ int s_shape[3];
+    double lo[3], hi[3], dm;
+    uint32_t fl;
+    block_bounds<4>(part, (n + kBoundsChunk - 1) / kBoundsChunk, s_bb, lo, hi, dm, fl);
+    if (threadIdx.x == 0) {
         const SimGeom g = geometry_from(lo, hi, dm, fl, n > 0, edge);
         publish_single(g, n, max_boxes, nb_cap, order, true, geom, hdr, start, s_geo, s_shape);
     }
@@ -567,10 +588,14 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
                                                  int32_t* __restrict__ start)
 {
     using Real = typename Mode<M>::Real;
+    using In = typename Mode<M>::In;
     __shared__ int32_t h[kBucketsMax];
     __shared__ int s_range[2];
     __shared__ SimGeom s_geo;
     __shared__ int s_shape[3];   // sb, nb, error
+    const unsigned tile = xcd_block();
+    const int64_t c0 = (int64_t)tile * kTileA;
+    const int64_t c1 = (c0 + kTileA < n) ? c0 + kTileA : n;
     int sb, nbk;
     if (BATCHED) {
         if (hdr->error) return;
@@ -601,25 +626,34 @@ __global__ __launch_bounds__(kTileThreads) void k_hist(const typename Mode<M>::I
         nbk = s_shape[1];
     }
     for (int b = threadIdx.x; b < nbk; b += kTileThreads) h[b] = 0;
-    const unsigned tile = xcd_block();
-    const int64_t c0 = (int64_t)tile * kTileA;
-    const int64_t c1 = (c0 + kTileA < n) ? c0 + kTileA : n;
     if (BATCHED && threadIdx.x == 0) {
         s_range[0] = find_sim(off, 0, B, c0);
         s_range[1] = find_sim(off, 0, B, c1 - 1);
     }
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kTileThreads) {
-        const int s = BATCHED ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
-        const SimGeom& g = BATCHED ? geom[s] : s_geo;
-        const double px = (double)(Real)x[i];
+    auto bin = [&](int64_t i, const SimGeom& g, In xi, In yi, In zi) {
+        const double px = (double)(Real)xi;
         const int ix = axis_index(px, g.origin[0], g.edge, g.dims[0]);
-        const int iy = axis_index((double)(Real)y[i], g.origin[1], g.edge, g.dims[1]);
-        const int iz = axis_index((double)(Real)z[i], g.origin[2], g.edge, g.dims[2]);
+        const int iy = axis_index((double)(Real)yi, g.origin[1], g.edge, g.dims[1]);
+        const int iz = axis_index((double)(Real)zi, g.origin[2], g.edge, g.dims[2]);
         const int key = g.box_base + ix + g.dims[0] * box_row(iy, iz, g.dims[1], g.tile_shift);
         box_id[i] = key;
         quarter[i] = (uint8_t)box_quarter(px, g.origin[0], 4.0 / g.edge, g.edge, ix);
-        atomicAdd(&h[key >> sb], 1);
+        // box-sorted input puts a whole wavefront in one bucket: one LDS
+        // atomic then counts it, instead of 64 on the same address
+        const int bk = key >> sb;
+        const int bf = __builtin_amdgcn_readfirstlane(bk);
+        const uint64_t act = __ballot(1);
+        if (__ballot(bk == bf) == act) {
+            if ((int)(threadIdx.x & (kWave - 1)) == (int)__ffsll((unsigned long long)act) - 1)
+                atomicAdd(&h[bf], (int)__popcll(act));
+        } else {
+            atomicAdd(&h[bk], 1);
+        }
+    };
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kTileThreads) {
+        const int s = BATCHED ? find_sim(off, s_range[0], s_range[1] + 1, i) : 0;
+        bin(i, BATCHED ? geom[s] : s_geo, x[i], y[i], z[i]);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nbk; b += kTileThreads)
