@@ -127,10 +127,13 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     gout = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(4))
     gkg = torch.empty(2, dtype=torch.float64, device="cuda")
     gin = tuple(torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3))
-    # launch shape of the gather (list length, block size) picked on this workload, outside the timed region
+    # row order of the boxes, then the launch shape of the gather (list
+    # length, block size), picked on this workload outside the timed region
     from paper_2105_00039_amd import autotune
-    ms.grid_build(ws, *t)
+    order = autotune.tune_box_order(ws, lambda: (ms.grid_build(ws, *t),
+                                                 ms.mech_step(ws, PARAMS, out=out)))
     ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
+    ws.tuning["box_order"] = order
 
     def one(ev=None, c=None):
         """One step from state buffer c (default: the current one)."""
@@ -707,7 +710,8 @@ def main():
             sx, _, wx, _ = time_plain(ms, torch, a, dt, args.steps, args.warmup, graph=True,
                                       sorted_state=sorted_head, **kw)
             c = wx.tuning["choice"]
-            return a[0].size * args.steps / sx, sx / args.steps * 1e3, dict(list=c[0], block=c[1])
+            return a[0].size * args.steps / sx, sx / args.steps * 1e3, dict(
+                list=c[0], block=c[1], box_order=wx.tuning["box_order"]["choice"])
 
         other = "f64" if args.dtype == "f32" else "f32"
         oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
@@ -769,7 +773,9 @@ def main():
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True,
                    "gather": dict(list=head_tuning["choice"][0], block=head_tuning["choice"][1]),
-                   "gather_ms": head_tuning["ms"]},
+                   "gather_ms": head_tuning["ms"],
+                   "box_order": head_tuning["box_order"]["choice"],
+                   "box_order_ms": head_tuning["box_order"]["ms"]},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
         "variants": extras, "fwd_bwd": fwd_bwd, "rollout_grad_adjoint262k": rollout_grad,
         "batched": batched, "host_state": host_state, "growing_population": growing,

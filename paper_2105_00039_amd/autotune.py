@@ -18,6 +18,11 @@ The default key is (dtype, agent count to the nearest power of two, mean box
 occupancy to the nearest half power of two, number of simulations).  Mean
 occupancy counts empty boxes, so a clustered population looks sparse by it;
 such callers pass their own ``key``.
+
+``tune_box_order`` times the row order of a single simulation's boxes (row-
+major or 16 x 16 tiles, the workspace's ``box_order``) the same way, over
+grid build + step, since the order changes both; forces and displacements do
+not depend on it either.
 """
 from __future__ import annotations
 
@@ -27,7 +32,7 @@ import os
 
 import torch
 
-from . import grid_info
+from . import MechStepError, device_status, grid_info
 
 # (contact-list length, threads per block); the first is the library default
 CHOICES = ((32, 256), (40, 256), (32, 128), (40, 128))
@@ -104,3 +109,59 @@ def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache
             json.dump(table, f, indent=1, sort_keys=True)
     return dict(key=key, choice=best, source="timed",
                 ms={f"{c[0]}/{c[1]}": t for c, t in times.items()})
+
+
+def _time(fn, reps):
+    fn()                                         # warm-up of this variant
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune_box_order(ws, build_and_step, key: str | None = None, reps: int = 5, cache=None,
+                   margin: float = 0.03) -> dict:
+    """Pick the faster row order ("rows" or "tiles") of a single simulation's
+    boxes for ``build_and_step`` (a callable running one grid build and one
+    step on the workspace, e.g. ``lambda: (grid_build(ws, x, y, z, d),
+    mech_step(ws, params, out=out))``) and set it as ``ws.box_order``.  The
+    order the automatic rule picks for this workload is kept unless the other
+    is faster by more than ``margin``.  The last call leaves a build in the
+    chosen order.  cache: as for :func:`tune` (entries "rows" / "tiles").
+    An order whose build fails (tiles whose padded box count exceeds the
+    workspace's max_boxes) is not chosen.
+    Returns {"key", "choice", "auto", "source", "ms": {order: ms per call}}."""
+    if ws.c.max_sims != 1:
+        raise ValueError("tune_box_order: batched builds always number rows row-major")
+    ws.box_order = "auto"
+    build_and_step()
+    auto = "tiles" if grid_info(ws)[0]["tile_shift"] else "rows"
+    key = (key or default_key(ws)) + "|order"
+    table, path = _load(cache)
+    if table.get(key) in ("rows", "tiles"):
+        ws.box_order = table[key]
+        build_and_step()
+        return dict(key=key, choice=table[key], auto=auto, source="cache", ms={})
+    other = "tiles" if auto == "rows" else "rows"
+    times = {}
+    for c in (auto, other):
+        ws.box_order = c
+        try:
+            build_and_step()
+            device_status(ws)
+        except MechStepError:
+            continue
+        times[c] = _time(build_and_step, reps)
+    best = other if other in times and times[other] * (1.0 + margin) < times[auto] else auto
+    ws.box_order = best
+    build_and_step()
+    table[key] = best
+    if path is not None:
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return dict(key=key, choice=best, auto=auto, source="timed", ms=times)
+

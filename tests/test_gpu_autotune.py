@@ -111,3 +111,39 @@ def test_tuner_picks_caches_and_rejects(tmp_path):
     ws.gather_block = 0
     ms.mech_step(ws, P)
     ms.device_status(ws)
+
+
+def test_box_order_tuner(tmp_path):
+    """tune_box_order times row-major against tiled rows over build + step,
+    keeps the automatic choice unless the other is faster, leaves a build in
+    the chosen order, caches the pick, and never picks an order whose build
+    fails; the displacements do not depend on the order."""
+    arrs = workloads.uniform(40000, mean_neighbors=12.0, seed=44).arrays()
+    n = len(arrs[0])
+    t = dev(arrs, "f32")
+    ref_ws = ms.Workspace(n, dtype="f32", box_order="rows")
+    ms.grid_build(ref_ws, *t)
+    ref = torch.stack(ms.mech_step(ref_ws, P)).cpu()
+    ws = ms.Workspace(n, dtype="f32")
+    out = tuple(torch.empty(n, dtype=ws.out_dtype, device="cuda") for _ in range(3))
+    step = lambda: (ms.grid_build(ws, *t), ms.mech_step(ws, P, out=out))
+    cache = tmp_path / "order.json"
+    r = autotune.tune_box_order(ws, step, cache=cache)
+    assert r["source"] == "timed" and r["auto"] == "rows" and r["choice"] in ("rows", "tiles")
+    assert set(r["ms"]) == {"rows", "tiles"}
+    assert ws.box_order == r["choice"]
+    assert ms.grid_info(ws)[0]["tile_shift"] == (4 if r["choice"] == "tiles" else 0)
+    assert torch.equal(torch.stack(out).cpu(), ref)
+    assert json.loads(cache.read_text())[r["key"]] == r["choice"]
+    ws2 = ms.Workspace(n, dtype="f32")
+    r2 = autotune.tune_box_order(ws2, lambda: (ms.grid_build(ws2, *t), ms.mech_step(ws2, P, out=out)),
+                                 cache=cache)
+    assert r2["source"] == "cache" and r2["choice"] == r["choice"] == ws2.box_order
+    # tiles that do not fit the workspace are never picked
+    small = ms.Workspace(n, dtype="f32", max_boxes=ms.grid_info(ref_ws)[0]["n_boxes"] + 1)
+    step_s = lambda: (ms.grid_build(small, *t), ms.mech_step(small, P, out=out))
+    r3 = autotune.tune_box_order(small, step_s)
+    assert r3["choice"] == "rows" and set(r3["ms"]) == {"rows"}
+    ms.device_status(small)
+    with pytest.raises(ValueError):
+        autotune.tune_box_order(ms.Workspace(n, max_sims=2, dtype="f32"), step)
