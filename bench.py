@@ -439,7 +439,8 @@ def time_batched(ms, torch, steps, warmup, seed=0, sorted_state=True):
     sec = a.elapsed_time(e) / 1e3
     return dict(value=n * steps / sec, unit="agent-steps/s", n_sims=b.n_sims, n_agents=n, steps=steps,
                 ms_per_step=sec / steps * 1e3, dtype="f32 force, f64 positions",
-                gather=dict(list=tuning["choice"][0], block=tuning["choice"][1]),
+                gather=dict(list=tuning["choice"][0], block=tuning["choice"][1],
+                            walk=tuning["choice"][2]),
                 state_order="box-sorted slot order" if sorted_state else "caller order",
                 workload="batched256: sizes 10^U(3,5), 4-30 neighbours, kappa U[1,4], gamma U[0.5,2]")
 
@@ -711,7 +712,7 @@ def main():
                                       sorted_state=sorted_head, **kw)
             c = wx.tuning["choice"]
             return a[0].size * args.steps / sx, sx / args.steps * 1e3, dict(
-                list=c[0], block=c[1], box_order=wx.tuning["box_order"]["choice"])
+                list=c[0], block=c[1], walk=c[2], box_order=wx.tuning["box_order"]["choice"])
 
         other = "f64" if args.dtype == "f32" else "f32"
         oarrs = [a.astype(np.float32 if other == "f32" else np.float64) for a in pop.arrays()]
@@ -772,7 +773,8 @@ def main():
                    "measured_neighbors": st["neighbors"], "contacts_per_agent": K,
                    "candidates_per_agent": st["candidates"], "n_boxes": st["n_boxes"],
                    "diameters": "U[8,12]", "params": PARAMS, "graph": True,
-                   "gather": dict(list=head_tuning["choice"][0], block=head_tuning["choice"][1]),
+                   "gather": dict(list=head_tuning["choice"][0], block=head_tuning["choice"][1],
+                                  walk=head_tuning["choice"][2]),
                    "gather_ms": head_tuning["ms"],
                    "box_order": head_tuning["box_order"]["choice"],
                    "box_order_ms": head_tuning["box_order"]["ms"]},

@@ -105,6 +105,21 @@ typedef enum {
                                 exceeds max_boxes */
 } ms_box_order;
 
+/* How the lanes of a wavefront walk their agents' 9 stencil runs (Section
+ * IV-B: one thread per agent) in the step and backward gathers.  Every lane
+ * meets its candidates in the same order either way, so the results are the
+ * same bit for bit; only the speed differs.
+ *   lanes:  each lane takes all of its runs in turn, so a wavefront steps as
+ *           often as its busiest lane has candidates in total (fastest on
+ *           uniform populations);
+ *   planes: the lanes take the three z-planes of the stencil together and
+ *           the three runs of a plane in turn, which keeps the lanes' loads
+ *           within one plane of slots (faster on dense clustered ones). */
+typedef enum {
+    MS_WALK_LANES = 0,
+    MS_WALK_PLANES = 1
+} ms_gather_walk;
+
 /* Force and displacement parameters (Section III, Eq. 1 and the text after it).
  *   kappa      repulsion coefficient
  *   gamma      attraction (adhesion) coefficient
@@ -131,8 +146,8 @@ typedef struct {
 
 /* Host-side description of a workspace.  Filled by ms_workspace_init; the
  * fields from n_agents to built are updated by the grid builds.  Treat them as
- * read-only; keep_forces, gather_list, gather_block, sorted_input and
- * box_order are the caller's to set. */
+ * read-only; keep_forces, gather_list, gather_block, sorted_input, box_order
+ * and gather_walk are the caller's to set. */
 typedef struct {
     void*   base;        /* device buffer, 256-byte aligned */
     size_t  bytes;
@@ -174,6 +189,11 @@ typedef struct {
                             (set by ms_workspace_init; auto), 1 row-major or 2
                             tiled rows (anything else: MS_EINVAL from the
                             builds).  Batched builds ignore it. */
+    int32_t gather_walk;  /* ms_gather_walk of the step and backward gathers:
+                            0 (set by ms_workspace_init) or 1 (anything else:
+                            MS_EINVAL from the step calls).  Results are
+                            identical bit for bit; the autotuner picks it with
+                            gather_list and gather_block. */
 } ms_workspace;
 
 /* Bytes of device memory a workspace with these capacities needs (0 for

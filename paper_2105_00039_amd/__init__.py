@@ -71,7 +71,8 @@ class Workspace:
 
     def __init__(self, max_agents: int, max_boxes: int | None = None, max_sims: int = 1,
                  dtype: str = "f32", device=None, keep_forces: bool = False,
-                 gather_list: int = 0, gather_block: int = 0, box_order: str = "auto"):
+                 gather_list: int = 0, gather_block: int = 0, box_order: str = "auto",
+                 gather_walk: str = "lanes"):
         self.lib = _lib.load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -92,6 +93,7 @@ class Workspace:
         self.gather_list = gather_list
         self.gather_block = gather_block
         self.box_order = box_order
+        self.gather_walk = gather_walk
         self.builds = 0   # grid builds issued on this workspace (the autograd layer checks it)
 
     @property
@@ -123,6 +125,22 @@ class Workspace:
     @sorted_input.setter
     def sorted_input(self, on: bool):
         self.c.sorted_input = 1 if on else 0
+
+    _WALKS = {"lanes": 0, "planes": 1}
+
+    @property
+    def gather_walk(self) -> str:
+        """How the gathers' lanes walk their 9 stencil runs: "lanes" (default;
+        each lane all of its runs in turn) or "planes" (the z-planes
+        together); results do not depend on it, speed does (see autotune)."""
+        return {v: k for k, v in self._WALKS.items()}.get(int(self.c.gather_walk),
+                                                          str(self.c.gather_walk))
+
+    @gather_walk.setter
+    def gather_walk(self, v: str):
+        if v not in self._WALKS:
+            raise ValueError(f"gather_walk must be one of {sorted(self._WALKS)}, not {v!r}")
+        self.c.gather_walk = self._WALKS[v]
 
     _BOX_ORDERS = {"auto": 0, "rows": 1, "tiles": 2}
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmechstep
 MS_OK, MS_EINVAL, MS_ECAPACITY, MS_EDEVICE, MS_EINPUT = 0, 1, 2, 3, 4
 MS_F32, MS_F64, MS_F32_POS64 = 0, 1, 2
 MS_BOX_ORDER_AUTO, MS_BOX_ORDER_ROWS, MS_BOX_ORDER_TILES = 0, 1, 2
+MS_WALK_LANES, MS_WALK_PLANES = 0, 1
 STATUS_NAMES = {0: "MS_OK", 1: "MS_EINVAL", 2: "MS_ECAPACITY", 3: "MS_EDEVICE", 4: "MS_EINPUT"}
 
 EXPORTS = (
@@ -52,7 +53,8 @@ class ms_workspace(ctypes.Structure):
                 ("n_agents", ctypes.c_int64), ("n_sims", ctypes.c_int32),
                 ("built", ctypes.c_int32), ("keep_forces", ctypes.c_int32),
                 ("gather_list", ctypes.c_int32), ("gather_block", ctypes.c_int32),
-                ("sorted_input", ctypes.c_int32), ("box_order", ctypes.c_int32)]
+                ("sorted_input", ctypes.c_int32), ("box_order", ctypes.c_int32),
+                ("gather_walk", ctypes.c_int32)]
 
 
 class MechStepError(RuntimeError):

@@ -1,14 +1,18 @@
 """Autotuner of the forward gather's launch shape.
 
 The force gather keeps each lane's contacts in a list in LDS and drains it
-into the Eq. 1 work before it can overflow.  Two knobs shape the launch:
+into the Eq. 1 work before it can overflow.  Three knobs shape the launch:
 
 * the list length (32 or 40 entries): a longer list drains less often, which
   pays when agents have many contacts (dense or clustered populations,
   FP64); a shorter one leaves LDS for more resident blocks;
 * the block size (256 or 128 threads): the list's LDS and the wavefronts
   come in smaller units, so more blocks are resident and the batched step's
-  per-block simulation lookup covers fewer agents.
+  per-block simulation lookup covers fewer agents;
+* the run walk ("lanes" or "planes"): each lane takes all of its agent's 9
+  stencil runs in turn (a wavefront then steps as often as its busiest lane
+  has candidates), or the lanes take the z-planes together (their loads stay
+  within one plane of slots, which pays on dense clustered populations).
 
 Results are identical bit for bit for every choice (each agent's contacts
 are summed in the same order by one lane), so the choice is decided by
@@ -34,8 +38,10 @@ import torch
 
 from . import MechStepError, device_status, grid_info
 
-# (contact-list length, threads per block); the first is the library default
-CHOICES = ((32, 256), (40, 256), (32, 128), (40, 128))
+# (contact-list length, threads per block, run walk); the first is the
+# library default
+CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (256, 128)
+                for lst in (32, 40))
 
 
 def default_key(ws) -> str:
@@ -59,27 +65,28 @@ def _load(cache):
 
 
 def _as_choice(v):
-    """A cached entry as a (list, block) pair (older caches hold the list only)."""
+    """A cached entry as a (list, block, walk) triple (older caches hold the
+    list only, or the list and block)."""
     if isinstance(v, (list, tuple)):
-        return (int(v[0]), int(v[1]))
-    return (int(v), 256)
+        return (int(v[0]), int(v[1]), str(v[2]) if len(v) > 2 else "lanes")
+    return (int(v), 256, "lanes")
 
 
 def _set(ws, c):
-    ws.gather_list, ws.gather_block = c
+    ws.gather_list, ws.gather_block, ws.gather_walk = c
 
 
 def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache=None,
          margin: float = 0.02) -> dict:
-    """Pick the fastest (list length, block size) for ``step`` (a callable
+    """Pick the fastest (list length, block size, run walk) for ``step`` (a callable
     running one force step on the workspace's current build, e.g. ``lambda:
     mech_step(ws, params, out=out)``) and set it on ``ws``.  The first of
     ``choices`` (the library default) is kept unless another is faster by more
     than ``margin``, so a tie does not flip the choice from run to run.
 
     cache: None, a dict, or the path of a JSON file (read if present, written
-    after a timed choice).  Returns {"key", "choice": (list, block), "source":
-    "cache" | "timed", "ms": {"list/block": mean ms per step}}."""
+    after a timed choice).  Returns {"key", "choice": (list, block, walk),
+    "source": "cache" | "timed", "ms": {"list/block/walk": mean ms per step}}."""
     choices = tuple(_as_choice(c) for c in choices)
     key = key or default_key(ws)
     table, path = _load(cache)
@@ -90,15 +97,7 @@ def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache
     times = {}
     for c in choices:
         _set(ws, c)
-        step()                                   # warm-up of this variant
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            step()
-        b.record()
-        torch.cuda.synchronize()
-        times[c] = a.elapsed_time(b) / reps
+        times[c] = _time(step, reps)
     best = min(times, key=times.get)
     if times[choices[0]] <= times[best] * (1.0 + margin):
         best = choices[0]
@@ -108,7 +107,7 @@ def tune(ws, step, key: str | None = None, choices=CHOICES, reps: int = 3, cache
         with open(path, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
     return dict(key=key, choice=best, source="timed",
-                ms={f"{c[0]}/{c[1]}": t for c, t in times.items()})
+                ms={f"{c[0]}/{c[1]}/{c[2]}": t for c, t in times.items()})
 
 
 def _time(fn, reps):

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
                                                      const typename Mode<M>::Pay* __restrict__ gin,
                                                      typename Mode<M>::Pay* __restrict__ fbar,
                                                      const typename Mode<M>::Pay* __restrict__ fsave,
-                                                     const uint2* __restrict__ payq)
+                                                     const uint2* __restrict__ payq, bool flat)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_fbar(const typename Mode<M>::Pay
     } else {
         force_sum<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                         pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                                        preq_of(payq, k), fx, fy, fz);
+                                        preq_of(payq, k), flat, fx, fy, fz);
     }
     const Pay gr = gin[perm[k]];
     const Real gx = gr.x, gy = gr.y, gz = gr.z;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
                                                        const Header* __restrict__ hdr,
                                                        typename Mode<M>::Pay* __restrict__ gout,
                                                        double* __restrict__ partials,
-                                                       const uint2* __restrict__ payq)
+                                                       const uint2* __restrict__ payq, bool flat)
 {
     using Real = typename Mode<M>::Real;
     using Pay = typename Mode<M>::Pay;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_gather(const typename Mode<M>::P
         Real px = 0, py = 0, pz = 0, rb = 0, kbl = 0, gbl = 0;
         scan_contacts<Real, Pay, LIST>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start,
                                             split, pay, lst + threadIdx.x,
-                                            preq_of(payq, k),
+                                            preq_of(payq, k), flat,
                                             [&](uint32_t off, const Pay& q) {
             // loaded before the contact test so a group's loads overlap
             Pay fj = *reinterpret_cast<const Pay*>(fbase + off);
@@ -323,7 +323,7 @@ template <int M, int LIST>
 hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                         const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
-                        double* g_params, bool acc, hipStream_t s)
+                        double* g_params, bool flat, bool acc, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using In = typename Mode<M>::In;
@@ -343,17 +343,19 @@ hipError_t backward_run(const Layout& L, const Dev& D, int64_t n, int32_t B, boo
                                                        (const Real*)gdz, n, D.hdr, rec);
     if (batched) {
         k_bwd_fbar<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, D.off, B, n,
-                                                   dummy, p_dev, D.hdr, rec, fb, nullptr, D.payq);
+                                                   dummy, p_dev, D.hdr, rec, fb, nullptr, D.payq,
+                                                   flat);
         k_bwd_gather<M, true, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, D.off, B,
-                                                     n, dummy, p_dev, D.hdr, rec, D.partials, D.payq);
+                                                     n, dummy, p_dev, D.hdr, rec, D.partials, D.payq,
+                                                     flat);
         k_reduce_params<<<B, kReduceThreads, 0, s>>>(D.partials, D.off, n, D.hdr, g_params, acc);
     } else {
         k_bwd_fbar<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, D.start, D.split, D.perm, D.geom, nullptr, 1,
                                                     n, *p_host, nullptr, D.hdr, rec, fb,
-                                                    static_cast<const Pay*>(D.fsave), D.payq);
+                                                    static_cast<const Pay*>(D.fsave), D.payq, flat);
         k_bwd_gather<M, false, LIST><<<nb, kBlock, 0, s>>>(pay, fb, D.start, D.split, D.perm, D.geom, nullptr,
                                                       1, n, *p_host, nullptr, D.hdr, rec,
-                                                      D.partials, D.payq);
+                                                      D.partials, D.payq, flat);
         k_reduce_params<<<1, kReduceThreads, 0, s>>>(D.partials, nullptr, n, D.hdr, g_params, acc);
     }
     if (acc)
@@ -370,13 +372,13 @@ template <int M>
 hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                          const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                          const void* gdy, const void* gdz, void* gx, void* gy, void* gz, void* gd,
-                         double* g_params, int list, bool acc, hipStream_t s)
+                         double* g_params, int list, bool flat, bool acc, hipStream_t s)
 {
     if (list == kLongList)
         return backward_run<M, kLongList>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
-                                          gz, gd, g_params, acc, s);
+                                          gz, gd, g_params, flat, acc, s);
     return backward_run<M, kMaxContacts>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy,
-                                         gz, gd, g_params, acc, s);
+                                         gz, gd, g_params, flat, acc, s);
 }
 
 }  // namespace
@@ -384,18 +386,19 @@ hipError_t backward_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bo
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, int list, bool acc, hipStream_t s)
+                           void* gd, double* g_params, int list, bool flat, bool acc,
+                           hipStream_t s)
 {
     switch (L.dtype) {
     case MS_F32:
         return backward_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, list, acc, s);
+                                     gd, g_params, list, flat, acc, s);
     case MS_F64:
         return backward_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx, gy, gz,
-                                     gd, g_params, list, acc, s);
+                                     gd, g_params, list, flat, acc, s);
     case MS_F32_POS64:
         return backward_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, gdx, gdy, gdz, gx,
-                                           gy, gz, gd, g_params, list, acc, s);
+                                           gy, gz, gd, g_params, list, flat, acc, s);
     default: return hipErrorInvalidValue;
     }
 }

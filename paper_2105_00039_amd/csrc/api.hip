@@ -120,6 +120,7 @@ ms_status ms_workspace_init(ms_workspace* ws, void* base, size_t bytes, int64_t 
     ws->sorted_input = 0;
     ws->gather_block = 0;
     ws->box_order = MS_BOX_ORDER_AUTO;
+    ws->gather_walk = MS_WALK_LANES;
     return check_hip(ms::launch_init(L, ms::resolve(L, base), as_stream(stream)), "ms_workspace_init");
 }
 
@@ -183,6 +184,8 @@ static int gather_block(const ms_workspace* ws)
     return ws->gather_block == ms::kForceBlockSmall ? ms::kForceBlockSmall : ms::kBlock;
 }
 
+static bool gather_flat(const ms_workspace* ws) { return ws->gather_walk != MS_WALK_PLANES; }
+
 static ms_status step_common(const ms_workspace* ws, int want_built, const char* who)
 {
     ms_status st = check_ws(ws, who);
@@ -195,6 +198,9 @@ static ms_status step_common(const ms_workspace* ws, int want_built, const char*
         ws->gather_block != ms::kBlock)
         return fail(MS_EINVAL, "%s: gather_block must be 0, %d or %d", who, ms::kForceBlockSmall,
                     ms::kBlock);
+    if (ws->gather_walk != MS_WALK_LANES && ws->gather_walk != MS_WALK_PLANES)
+        return fail(MS_EINVAL, "%s: gather_walk must be %d or %d", who, MS_WALK_LANES,
+                    MS_WALK_PLANES);
     if (ws->built != want_built)
         return fail(MS_EINVAL, "%s: workspace holds no %s grid build", who,
                     want_built == 1 ? "plain" : "batched");
@@ -214,7 +220,8 @@ ms_status ms_mech_step(const ms_workspace* ws, const ms_params* p, void* dx, voi
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
                                       dz, nullptr, nullptr, nullptr, ws->keep_forces != 0,
-                                      gather_list(ws), gather_block(ws), as_stream(stream)),
+                                      gather_list(ws), gather_block(ws), gather_flat(ws),
+                                      as_stream(stream)),
                      who);
 }
 
@@ -244,7 +251,7 @@ ms_status ms_mech_step_integrate(const ms_workspace* ws, const ms_params* p, voi
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, 1, false, p, nullptr, dx, dy,
                                       dz, x, y, z, ws->keep_forces != 0, gather_list(ws),
-                                      gather_block(ws),
+                                      gather_block(ws), gather_flat(ws),
                                       as_stream(stream)),
                      who);
 }
@@ -289,7 +296,7 @@ static ms_status step_sorted_common(ms_workspace* ws, bool batched, const ms_par
                                       batched, batched ? nullptr : p, batched ? p : nullptr, dx, dy,
                                       dz, nullptr, nullptr, nullptr,
                                       !batched && ws->keep_forces != 0, gather_list(ws),
-                                      gather_block(ws),
+                                      gather_block(ws), gather_flat(ws),
                                       as_stream(stream), &so),
                      who);
 }
@@ -326,7 +333,8 @@ ms_status ms_mech_step_batched(const ms_workspace* ws, const ms_params* params, 
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
                                       params, dx, dy, dz, nullptr, nullptr, nullptr, false,
-                                      gather_list(ws), gather_block(ws), as_stream(stream)),
+                                      gather_list(ws), gather_block(ws), gather_flat(ws),
+                                      as_stream(stream)),
                      who);
 }
 
@@ -344,7 +352,7 @@ ms_status ms_mech_step_batched_integrate(const ms_workspace* ws, const ms_params
     const ms::Layout L = ms::make_layout(ws->max_agents, ws->max_boxes, ws->max_sims, ws->dtype);
     return check_hip(ms::launch_force(L, ms::resolve(L, ws->base), n, ws->n_sims, true, nullptr,
                                       params, dx, dy, dz, x, y, z, false, gather_list(ws),
-                                      gather_block(ws),
+                                      gather_block(ws), gather_flat(ws),
                                       as_stream(stream)),
                      who);
 }
@@ -372,8 +380,8 @@ static ms_status backward_common(const ms_workspace* ws, bool batched, const ms_
         return st;
     return check_hip(ms::launch_backward(L, ms::resolve(L, ws->base), n, batched ? ws->n_sims : 1,
                                          batched, batched ? nullptr : p, batched ? p : nullptr, gdx,
-                                         gdy, gdz, gx, gy, gz, gd, g_params, gather_list(ws), acc,
-                                         as_stream(stream)),
+                                         gdy, gdz, gx, gy, gz, gd, g_params, gather_list(ws),
+                                         gather_flat(ws), acc, as_stream(stream)),
                      who);
 }
 
@@ -647,7 +655,7 @@ ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, cons
                                   MS_BOX_ORDER_AUTO, s);
     if (e == hipSuccess && n > 0)
         e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
-                             false, ms::kMaxContacts, ms::kBlock, s);
+                             false, ms::kMaxContacts, ms::kBlock, true, s);
     if (e == hipSuccess && dev_error) e = ms::launch_error_copy(D, dev_error, s);
     return check_hip(e, who);
 }

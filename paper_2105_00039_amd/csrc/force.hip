@@ -47,7 +47,8 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
                                                   typename Mode<M>::Pay* __restrict__ dout,
                                                   typename Mode<M>::Pay* __restrict__ fsave,
                                                   const uint2* __restrict__ payq,
-                                                  SortedOut<typename Mode<M>::In, typename Mode<M>::Real> so)
+                                                  SortedOut<typename Mode<M>::In, typename Mode<M>::Real> so,
+                                                  bool flat)
 {
     using Real = typename Mode<M>::Real;
     using In = typename Mode<M>::In;
@@ -79,7 +80,7 @@ __attribute__((amdgpu_waves_per_eu(M == MS_F64 && !BATCHED ? 4 : 1))) void k_for
     Real fx, fy, fz;
     force_sum<Real, Pay, LIST, NT>(g, c, pi, (uint32_t)(k * (int64_t)sizeof(Pay)), start, split,
                                     pay, (Real)P.kappa, (Real)P.gamma, lst + threadIdx.x,
-                                    preq_of(payq, k), fx, fy, fz);
+                                    preq_of(payq, k), flat, fx, fy, fz);
     if (fsave) {
         Pay f;
         f.x = fx; f.y = fy; f.z = fz; f.w = (Real)0;
@@ -307,13 +308,14 @@ __global__ __launch_bounds__(kBlock) void k_copy(const uint4* __restrict__ src, 
 template <int M, bool BATCHED, int LIST, bool SORTED, int NT>
 void launch_k_force(const Dev& D, int64_t n, int32_t B, const ms_params& p1, const ms_params* p_dev,
                     typename Mode<M>::Pay* rec, typename Mode<M>::Pay* fs,
-                    const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, hipStream_t s)
+                    const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, bool flat,
+                    hipStream_t s)
 {
     using Pay = typename Mode<M>::Pay;
     const unsigned nb = (unsigned)((n + NT - 1) / NT);
     k_force<M, BATCHED, LIST, SORTED, NT><<<nb, NT, 0, s>>>(
         static_cast<const Pay*>(D.payload), D.start, D.split, D.perm, D.geom, BATCHED ? D.off : nullptr,
-        B, n, p1, p_dev, D.hdr, rec, fs, D.payq, so);
+        B, n, p1, p_dev, D.hdr, rec, fs, D.payq, so, flat);
 }
 
 template <int M, bool BATCHED, bool SORTED, int NT>
@@ -321,12 +323,13 @@ void launch_k_force_nt(const Dev& D, int64_t n, int32_t B, const ms_params& p1,
                        const ms_params* p_dev, typename Mode<M>::Pay* rec,
                        typename Mode<M>::Pay* fs,
                        const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, int list,
-                       hipStream_t s)
+                       bool flat, hipStream_t s)
 {
     if (list == kLongList)
-        launch_k_force<M, BATCHED, kLongList, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, s);
+        launch_k_force<M, BATCHED, kLongList, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, flat, s);
     else
-        launch_k_force<M, BATCHED, kMaxContacts, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, s);
+        launch_k_force<M, BATCHED, kMaxContacts, SORTED, NT>(D, n, B, p1, p_dev, rec, fs, so, flat,
+                                                              s);
 }
 
 // The forward gather's launch shape chosen per workspace: contact-list length
@@ -336,25 +339,27 @@ void launch_k_force_list(const Dev& D, int64_t n, int32_t B, bool batched, const
                          const ms_params* p_dev, typename Mode<M>::Pay* rec,
                          typename Mode<M>::Pay* fs,
                          const SortedOut<typename Mode<M>::In, typename Mode<M>::Real>& so, int list,
-                         int nt, hipStream_t s)
+                         int nt, bool flat, hipStream_t s)
 {
     if (batched && nt == kForceBlockSmall)
         launch_k_force_nt<M, true, SORTED, kForceBlockSmall>(D, n, B, p1, p_dev, rec, nullptr, so,
-                                                             list, s);
+                                                             list, flat, s);
     else if (batched)
-        launch_k_force_nt<M, true, SORTED, kBlock>(D, n, B, p1, p_dev, rec, nullptr, so, list, s);
+        launch_k_force_nt<M, true, SORTED, kBlock>(D, n, B, p1, p_dev, rec, nullptr, so, list,
+                                                   flat, s);
     else if (nt == kForceBlockSmall)
         launch_k_force_nt<M, false, SORTED, kForceBlockSmall>(D, n, 1, p1, nullptr, rec, fs, so,
-                                                              list, s);
+                                                              list, flat, s);
     else
-        launch_k_force_nt<M, false, SORTED, kBlock>(D, n, 1, p1, nullptr, rec, fs, so, list, s);
+        launch_k_force_nt<M, false, SORTED, kBlock>(D, n, 1, p1, nullptr, rec, fs, so, list, flat,
+                                                    s);
 }
 
 template <int M>
 hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                       const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
                       void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
-                      const SortedState* sorted, hipStream_t s)
+                      bool flat, const SortedState* sorted, hipStream_t s)
 {
     using Real = typename Mode<M>::Real;
     using In = typename Mode<M>::In;
@@ -373,10 +378,10 @@ hipError_t force_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool 
         so.dx = X; so.dy = Y; so.dz = Z;
         so.xi = static_cast<const In*>(sorted->x_in); so.yi = static_cast<const In*>(sorted->y_in);
         so.zi = static_cast<const In*>(sorted->z_in); so.di = static_cast<const In*>(sorted->d_in);
-        launch_k_force_list<M, true>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, s);
+        launch_k_force_list<M, true>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, flat, s);
         return hipGetLastError();
     }
-    launch_k_force_list<M, false>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, s);
+    launch_k_force_list<M, false>(D, n, B, batched, p1, p_dev, A, fs, so, list, nt, flat, s);
     if (px) {
         k_soa_integrate<Pay, Real, In><<<nb, kBlock, 0, s>>>(A, n, D.hdr, X, Y, Z, static_cast<In*>(px),
                                                              static_cast<In*>(py),
@@ -426,18 +431,18 @@ hipError_t nbr_mode(const Layout& L, const Dev& D, int64_t n, int32_t B, bool ba
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
                         void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
-                        hipStream_t s, const SortedState* sorted)
+                        bool flat, hipStream_t s, const SortedState* sorted)
 {
     switch (L.dtype) {
     case MS_F32:
         return force_mode<MS_F32>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, nt, sorted, s);
+                                  list, nt, flat, sorted, s);
     case MS_F64:
         return force_mode<MS_F64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz, keep,
-                                  list, nt, sorted, s);
+                                  list, nt, flat, sorted, s);
     case MS_F32_POS64:
         return force_mode<MS_F32_POS64>(L, D, n, B, batched, p_host, p_dev, dx, dy, dz, px, py, pz,
-                                        keep, list, nt, sorted, s);
+                                        keep, list, nt, flat, sorted, s);
     default: return hipErrorInvalidValue;
     }
 }

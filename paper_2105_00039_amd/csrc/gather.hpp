@@ -342,14 +342,16 @@ __device__ __forceinline__ bool quant_hit(const PreQ& p, uint2 q)
 // overflow any lane's list, so pairs are handed over in candidate order.
 // Offsets are 32-bit: a workspace holds fewer than 2^32 payload bytes.
 // The scan reads the quantised slot copy `pre`; the list holds copy offsets,
-// scaled to payload offsets when drained.
+// scaled to payload offsets when drained.  `flat` (uniform over the launch)
+// picks how the lanes walk their 9 runs; each lane meets its candidates in
+// the same order either way, so the results are the same bit for bit.
 template <typename Real, typename Pay, int LIST = kMaxContacts, int NT = kBlock, typename OnPair>
 __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pay& pi,
                                               uint32_t self_off,
                                               const int32_t* __restrict__ start,
                                               const uint32_t* __restrict__ split,
                                               const Pay* __restrict__ pay, uint32_t* lst,
-                                              const PreQ& pre, OnPair&& on_pair)
+                                              const PreQ& pre, bool flat, OnPair&& on_pair)
 {
     constexpr uint32_t P = (uint32_t)sizeof(Pay);
     constexpr uint32_t PS = (uint32_t)sizeof(uint2);   // bytes per scanned candidate
@@ -396,14 +398,75 @@ __device__ __forceinline__ void scan_contacts(const SimGeom& g, Cell c, const Pa
         test(q2, off + 2 * PS, off + 2 * PS < end);
         test(q3, off + 3 * PS, off + 3 * PS < end);
     };
+    if (flat) {
+        // Each lane walks its own runs one after another, so a wavefront
+        // takes as many steps as its busiest lane has groups in all 9 runs
+        // together, not the sum over the runs of the busiest lane's groups
+        // in each.  The non-empty runs wait at the top of the lane's list
+        // (begin and end, two entries each, in stencil order); the hits fill
+        // the list from the bottom, below the runs not taken yet.
+        static_assert(LIST >= 2 * 9 + 4, "room for the runs and a group of four");
+        int nr = 0;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-        const uint32_t end = (uint32_t)R.e[r] * PS;
-        for (uint32_t off = (uint32_t)R.b[r] * PS; off < end; off += 4 * PS) {
-            // the whole wave drains when any lane's list is nearly full: the
-            // lanes' drains run side by side instead of one after another
-            if (__any(cnt > LIST - 4)) drain();
-            group(off, end);
+        for (int r = 0; r < 9; ++r) nr += R.e[r] > R.b[r] ? 1 : 0;
+        {
+            int p = LIST - 2 * nr;
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                if (R.e[r] > R.b[r]) {
+                    lst[p * NT] = (uint32_t)R.b[r] * PS;
+                    lst[(p + 1) * NT] = (uint32_t)R.e[r] * PS;
+                    p += 2;
+                }
+            }
+        }
+        int left = nr;   // runs still waiting in the list
+        uint32_t off = 0, end = 0;
+        auto next_run = [&]() {
+            if (left > 0) {
+                const int p = LIST - 2 * left;
+                off = lst[p * NT];
+                end = lst[(p + 1) * NT];
+                --left;
+            }
+        };
+        next_run();
+        while (__any(off < end)) {
+            // the whole wave drains when any lane's next group could reach
+            // its waiting runs: the lanes' drains run side by side
+            if (__any(cnt > LIST - 4 - 2 * left)) drain();
+            if (off < end) {
+                group(off, end);
+                off += 4 * PS;
+                if (off >= end) next_run();
+            }
+        }
+    } else {
+        // The lanes take the z-planes together and walk the three runs of
+        // a plane one after another: fewer steps than run by run, while the
+        // lanes' loads stay within one plane of slots (on dense populations
+        // the flat walk spreads them over all three and loses more to the
+        // memory path than it saves in steps).
+#pragma unroll
+        for (int pz = 0; pz < 3; ++pz) {
+            const uint32_t b0 = (uint32_t)R.b[3 * pz] * PS, e0 = (uint32_t)R.e[3 * pz] * PS;
+            const uint32_t b1 = (uint32_t)R.b[3 * pz + 1] * PS, e1 = (uint32_t)R.e[3 * pz + 1] * PS;
+            const uint32_t b2 = (uint32_t)R.b[3 * pz + 2] * PS, e2 = (uint32_t)R.e[3 * pz + 2] * PS;
+            uint32_t off = b0, end = e0;
+            int k = 0;
+            auto advance = [&]() {
+                if (off >= end && k == 0) { k = 1; off = b1; end = e1; }
+                if (off >= end && k == 1) { k = 2; off = b2; end = e2; }
+            };
+            advance();
+            while (__any(off < end)) {
+                if (__any(cnt > LIST - 4)) drain();
+                if (off < end) {
+                    group(off, end);
+                    off += 4 * PS;
+                    advance();
+                }
+            }
         }
     }
     drain();
@@ -417,11 +480,11 @@ __device__ __forceinline__ void force_sum(const SimGeom& g, Cell c, const Pay& p
                                           uint32_t self_off, const int32_t* __restrict__ start,
                                           const uint32_t* __restrict__ split,
                                           const Pay* __restrict__ pay, Real kap, Real gam,
-                                          uint32_t* lst, const PreQ& pre, Real& fx, Real& fy,
-                                          Real& fz)
+                                          uint32_t* lst, const PreQ& pre, bool flat, Real& fx,
+                                          Real& fy, Real& fz)
 {
     Real ax = 0, ay = 0, az = 0;
-    scan_contacts<Real, Pay, LIST, NT>(g, c, pi, self_off, start, split, pay, lst, pre,
+    scan_contacts<Real, Pay, LIST, NT>(g, c, pi, self_off, start, split, pay, lst, pre, flat,
                                         [&](uint32_t, const Pay& q) {
         contact_force(pi, q, kap, gam, ax, ay, az);
     });

@@ -40,19 +40,22 @@ struct SortedState {
 // in slot order; px/py/pz unused).  keep (single only): also store the
 // forces for the backward step.  list: contact-list length of the gather
 // (kMaxContacts or kLongList); nt: threads per block of the gather
-// (kForceBlockSmall or kBlock).
+// (kForceBlockSmall or kBlock); flat: how the gather's lanes walk their runs
+// (each lane all of its runs in turn, or the z-planes together; same results).
 hipError_t launch_force(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                         const ms_params* p_host, const ms_params* p_dev, void* dx, void* dy,
                         void* dz, void* px, void* py, void* pz, bool keep, int list, int nt,
-                        hipStream_t s, const SortedState* sorted = nullptr);
+                        bool flat, hipStream_t s, const SortedState* sorted = nullptr);
 
-// Backward step; list: contact-list length of its gathers (as launch_force).
+// Backward step; list, flat: contact-list length and run walk of its gathers
+// (as launch_force).
 // acc: rollout mode, gdx..gdz == gx..gz are the position gradients of the
 // state type, updated in place (pbar += J^T pbar); gd and g_params are added to.
 hipError_t launch_backward(const Layout& L, const Dev& D, int64_t n, int32_t B, bool batched,
                            const ms_params* p_host, const ms_params* p_dev, const void* gdx,
                            const void* gdy, const void* gdz, void* gx, void* gy, void* gz,
-                           void* gd, double* g_params, int list, bool acc, hipStream_t s);
+                           void* gd, double* g_params, int list, bool flat, bool acc,
+                           hipStream_t s);
 
 hipError_t launch_integrate(void* x, void* y, void* z, const void* dx, const void* dy,
                             const void* dz, int64_t n, int dtype, hipStream_t s);

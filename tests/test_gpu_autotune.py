@@ -1,9 +1,9 @@
 """The forward gather's launch shape (the autotuner's knobs: contact-list
-length and block size) does not change any result: plain, fused, sorted and
-batched steps and the backward are bitwise identical for every allowed
-choice; the tuner picks an allowed (length, block) pair, caches it under its
-key (dict or JSON file) and reuses it; other values are rejected through the
-C ABI."""
+length, block size and run walk) does not change any result: plain, fused,
+sorted and batched steps and the backward are bitwise identical for every
+allowed choice; the tuner picks an allowed (length, block, walk) triple,
+caches it under its key (dict or JSON file) and reuses it; other values are
+rejected through the C ABI.  The box-order tuner is checked here too."""
 import json
 
 import numpy as np
@@ -48,7 +48,7 @@ def test_launch_shape_does_not_change_results(case, mode):
     g = [torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3)]
     res = {}
     for c in autotune.CHOICES:
-        ws.gather_list, ws.gather_block = c
+        ws.gather_list, ws.gather_block, ws.gather_walk = c
         D = [a.clone() for a in ms.mech_step(ws, P)]
         G = [a.clone() for a in ms.mech_step_backward(ws, P, *g)[:4]]
         pos = [a.clone() for a in t[:3]]
@@ -69,7 +69,7 @@ def test_launch_shape_batched():
     ms.grid_build_batched(ws, *dev(b.arrays(), "f32_pos64"), ms.BatchSpec(b.offsets))
     out = {}
     for c in autotune.CHOICES:
-        ws.gather_list, ws.gather_block = c
+        ws.gather_list, ws.gather_block, ws.gather_walk = c
         out[c] = [a.clone() for a in ms.mech_step_batched(ws, Pd)]
     ms.device_status(ws)
     for c in autotune.CHOICES[1:]:
@@ -90,16 +90,23 @@ def test_tuner_picks_caches_and_rejects(tmp_path):
     table = {}
     r = autotune.tune(ws, step, cache=table)
     assert r["source"] == "timed" and r["choice"] in autotune.CHOICES
-    assert (ws.gather_list, ws.gather_block) == r["choice"]
+    assert (ws.gather_list, ws.gather_block, ws.gather_walk) == r["choice"]
     assert tuple(table[r["key"]]) == r["choice"] and len(r["ms"]) == len(autotune.CHOICES)
-    ws.gather_list, ws.gather_block = 0, 0
+    ws.gather_list, ws.gather_block, ws.gather_walk = 0, 0, "lanes"
     r2 = autotune.tune(ws, step, cache=table)
-    assert r2["source"] == "cache" and (ws.gather_list, ws.gather_block) == r["choice"]
+    assert r2["source"] == "cache"
+    assert (ws.gather_list, ws.gather_block, ws.gather_walk) == r["choice"]
     path = tmp_path / "tune.json"
     r3 = autotune.tune(ws, step, key="custom", cache=path)
     assert r3["source"] == "timed" and tuple(json.loads(path.read_text())["custom"]) == r3["choice"]
     r4 = autotune.tune(ws, step, key="custom", cache=path)
     assert r4["source"] == "cache" and r4["choice"] == r3["choice"]
+    ws.c.gather_walk = 2
+    with pytest.raises(ms.MechStepError, match="gather_walk"):
+        ms.mech_step(ws, P)
+    with pytest.raises(ValueError):
+        ws.gather_walk = "rows"
+    ws.gather_walk = "lanes"
     ws.gather_list = 33
     with pytest.raises(ms.MechStepError) as ei:
         ms.mech_step(ws, P)
