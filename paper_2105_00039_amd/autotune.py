@@ -6,8 +6,9 @@ into the Eq. 1 work before it can overflow.  Three knobs shape the launch:
 * the list length (32 or 40 entries): a longer list drains less often, which
   pays when agents have many contacts (dense or clustered populations,
   FP64); a shorter one leaves LDS for more resident blocks;
-* the block size (256 or 128 threads): the list's LDS and the wavefronts
-  come in smaller units, so more blocks are resident and the batched step's
+* the block size (256 or 64 threads): the list's LDS and the wavefronts
+  come in smaller units (one wavefront per block at 64), so blocks finish
+  and are replaced one wavefront at a time and the batched step's
   per-block simulation lookup covers fewer agents;
 * the run walk ("lanes" or "planes"): each lane takes all of its agent's 9
   stencil runs in turn (a wavefront then steps as often as its busiest lane
@@ -40,7 +41,7 @@ from . import MechStepError, device_status, grid_info
 
 # (contact-list length, threads per block, run walk); the first is the
 # library default
-CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (256, 128)
+CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (256, 64)
                 for lst in (32, 40))
 
 

@@ -24,7 +24,7 @@ constexpr int kSortThreads = 512;     // threads per block of the per-bucket sor
 constexpr int kSortStage = 4096;      // buckets up to this many agents are sorted in LDS
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
-constexpr int kForceBlockSmall = 128; // the smaller block the forward gather may use
+constexpr int kForceBlockSmall = 64;  // the smaller block the forward gather may use
 constexpr int kRowTileShift = 4;      // tiled x-rows: 16 x 16 tiles of (iy, iz)
 constexpr int64_t kTilePlaneAgents = 49152;   // agents per z-plane from which a build tiles its rows
 // Quantised slot copy of plain builds (the gather's candidate test): quanta

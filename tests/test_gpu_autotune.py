@@ -111,7 +111,7 @@ def test_tuner_picks_caches_and_rejects(tmp_path):
     with pytest.raises(ms.MechStepError) as ei:
         ms.mech_step(ws, P)
     assert ei.value.status == ms._lib.MS_EINVAL
-    ws.gather_list, ws.gather_block = 0, 64
+    ws.gather_list, ws.gather_block = 0, 128
     with pytest.raises(ms.MechStepError) as ei:
         ms.mech_step(ws, P)
     assert ei.value.status == ms._lib.MS_EINVAL

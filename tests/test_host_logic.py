@@ -62,6 +62,7 @@ def test_autotune_cache_loading(tmp_path):
     # threads, each lane walking its runs in turn; every triple appears once
     assert autotune.CHOICES[0] == (32, 256, "lanes")
     assert len(set(autotune.CHOICES)) == len(autotune.CHOICES) == 8
+    assert {c[1] for c in autotune.CHOICES} == {64, 256}
     # entries of older caches (list length only, or list and block) read with
     # the default block size and walk
     assert autotune._as_choice(40) == (40, 256, "lanes")
