@@ -172,7 +172,7 @@ typedef struct {
                             per CU.  Results are identical bit for bit; the
                             package's autotuner picks the faster one. */
     int32_t gather_block; /* threads per block of the forward gather: 0 (set by
-                            ms_workspace_init; means 256), 64 or 256 (anything
+                            ms_workspace_init; means 64), 64 or 256 (anything
                             else: MS_EINVAL from the step calls).  Results are
                             identical bit for bit; the autotuner picks it with
                             gather_list. */

@@ -108,7 +108,7 @@ class Workspace:
 
     @property
     def gather_block(self) -> int:
-        """Threads per block of the forward gather (0 = default 256, or 64 or
+        """Threads per block of the forward gather (0 = default 64, or 64 or
         256); results do not depend on it, speed does (see autotune)."""
         return int(self.c.gather_block)
 

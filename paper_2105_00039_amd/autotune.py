@@ -41,7 +41,7 @@ from . import MechStepError, device_status, grid_info
 
 # (contact-list length, threads per block, run walk); the first is the
 # library default
-CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (256, 64)
+CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (64, 256)
                 for lst in (32, 40))
 
 
@@ -70,7 +70,7 @@ def _as_choice(v):
     list only, or the list and block)."""
     if isinstance(v, (list, tuple)):
         return (int(v[0]), int(v[1]), str(v[2]) if len(v) > 2 else "lanes")
-    return (int(v), 256, "lanes")
+    return (int(v), 64, "lanes")
 
 
 def _set(ws, c):

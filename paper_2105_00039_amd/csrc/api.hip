@@ -181,7 +181,7 @@ static int gather_list(const ms_workspace* ws)
 
 static int gather_block(const ms_workspace* ws)
 {
-    return ws->gather_block == ms::kForceBlockSmall ? ms::kForceBlockSmall : ms::kBlock;
+    return ws->gather_block == ms::kBlock ? ms::kBlock : ms::kForceBlockSmall;
 }
 
 static bool gather_flat(const ms_workspace* ws) { return ws->gather_walk != MS_WALK_PLANES; }
@@ -655,7 +655,7 @@ ms_status ms_mech_step_noalloc(const void* x, const void* y, const void* z, cons
                                   MS_BOX_ORDER_AUTO, s);
     if (e == hipSuccess && n > 0)
         e = ms::launch_force(L, D, n, 1, false, p, nullptr, dx, dy, dz, nullptr, nullptr, nullptr,
-                             false, ms::kMaxContacts, ms::kBlock, true, s);
+                             false, ms::kMaxContacts, ms::kForceBlockSmall, true, s);
     if (e == hipSuccess && dev_error) e = ms::launch_error_copy(D, dev_error, s);
     return check_hip(e, who);
 }
