@@ -105,7 +105,7 @@ def contacts_per_agent(x, y, z, d, counts, lst):
 
 
 def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, backward=False,
-               sorted_state=False):
+               sorted_state=False, gather=None):
     """Returns (seconds for `steps` steps, mean force-step ms or None, ws, state).
 
     A step is grid build + force + displacement + integrate.  sorted_state:
@@ -128,12 +128,21 @@ def time_plain(ms, torch, arrs, dtype, steps, warmup, graph=True, events=False, 
     gkg = torch.empty(2, dtype=torch.float64, device="cuda")
     gin = tuple(torch.full((n,), 1e-3, dtype=ws.out_dtype, device="cuda") for _ in range(3))
     # row order of the boxes, then the launch shape of the gather (list
-    # length, block size), picked on this workload outside the timed region
+    # length, block size, run walk), picked on this workload outside the
+    # timed region; `gather` fixes the launch shape instead (and leaves the
+    # box order to the library's rule), so that the separate processes of a
+    # profiling session all run the same kernel
     from paper_2105_00039_amd import autotune
-    order = autotune.tune_box_order(ws, lambda: (ms.grid_build(ws, *t),
-                                                 ms.mech_step(ws, PARAMS, out=out)))
-    ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
-    ws.tuning["box_order"] = order
+    if gather is not None:
+        ws.gather_list, ws.gather_block, ws.gather_walk = gather
+        ms.grid_build(ws, *t)
+        ws.tuning = dict(choice=tuple(gather), ms={}, source="fixed",
+                         box_order=dict(choice="auto", ms={}))
+    else:
+        order = autotune.tune_box_order(ws, lambda: (ms.grid_build(ws, *t),
+                                                     ms.mech_step(ws, PARAMS, out=out)))
+        ws.tuning = autotune.tune(ws, lambda: ms.mech_step(ws, PARAMS, out=out))
+        ws.tuning["box_order"] = order
 
     def one(ev=None, c=None):
         """One step from state buffer c (default: the current one)."""
@@ -597,6 +606,10 @@ def main():
                          "batched line's 256 simulations, graph-replayed steps)")
     ap.add_argument("--backward", action="store_true",
                     help="with --profile-only: eager steps with the backward step as well")
+    ap.add_argument("--gather", default=None, metavar="LIST/BLOCK/WALK",
+                    help="with --profile-only: fixed launch shape of the gather (e.g. 32/64/lanes) "
+                         "instead of the autotuner's pick, so that every profiling pass runs the "
+                         "same kernel")
     ap.add_argument("--order", default="sorted", choices=["sorted", "caller"],
                     help="state order of the rollout: the build's slot order (sorted, the "
                          "headline) or the caller's order")
@@ -637,8 +650,13 @@ def main():
             arrs = [a.astype(np.float32) for a in cl.arrays()]
             args.dtype = "f32"
             log(f"workload clusters16M f32: {arrs[0].size} agents")
+        fixed = None
+        if args.gather:
+            lst, nt, walk = args.gather.split("/")
+            fixed = (int(lst), int(nt), walk)
         sec, fms, ws, _ = time_plain(ms, torch, arrs, args.dtype, args.steps, args.warmup, events=True,
-                                     backward=args.backward, sorted_state=args.order == "sorted")
+                                     backward=args.backward, sorted_state=args.order == "sorted",
+                                     gather=fixed)
         log(f"eager {args.steps} steps: {sec * 1e3 / args.steps:.3f} ms/step, force {fms * 1e3:.1f} us")
         if args.probe_copy:
             nbytes = args.probe_copy << 20

@@ -25,6 +25,7 @@ constexpr int kSortStage = 4096;      // buckets up to this many agents are sort
 constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
 constexpr int kForceBlockSmall = 64;  // the smaller block the forward gather may use
+constexpr int kBwdBlock = 64;         // threads per block of the backward gather
 constexpr int kRowTileShift = 4;      // tiled x-rows: 16 x 16 tiles of (iy, iz)
 constexpr int64_t kTilePlaneAgents = 49152;   // agents per z-plane from which a build tiles its rows
 // Quantised slot copy of plain builds (the gather's candidate test): quanta
@@ -122,7 +123,7 @@ constexpr Layout make_layout(int64_t max_agents, int64_t max_boxes, int32_t max_
     L.nblk_b_max = (na + kBoundsChunk - 1) / kBoundsChunk;
     int64_t nbc = (max_boxes + (1 << kSBMin) - 1) >> kSBMin;
     L.nb_cap = nbc < kBucketsMax ? (nbc > 0 ? nbc : 1) : kBucketsMax;
-    L.n_part = nblk + max_sims + 1;
+    L.n_part = (na + kBwdBlock - 1) / kBwdBlock + max_sims + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
     L.hdr = take(sizeof(Header));
