@@ -165,7 +165,7 @@ typedef struct {
                             they belong to the current build and the same
                             parameters.  Results are identical either way. */
     int32_t gather_list; /* contact-list length of the step's gathers: 0 (set by
-                            ms_workspace_init; means 32), 32 or 40 entries per
+                            ms_workspace_init; means 24), 24 or 40 entries per
                             lane (anything else: MS_EINVAL from the step calls).
                             Longer lists drain less often, which pays on dense
                             populations; shorter ones leave LDS for more blocks

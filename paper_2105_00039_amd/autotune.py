@@ -3,7 +3,7 @@
 The force gather keeps each lane's contacts in a list in LDS and drains it
 into the Eq. 1 work before it can overflow.  Three knobs shape the launch:
 
-* the list length (32 or 40 entries): a longer list drains less often, which
+* the list length (24 or 40 entries): a longer list drains less often, which
   pays when agents have many contacts (dense or clustered populations,
   FP64); a shorter one leaves LDS for more resident blocks;
 * the block size (256 or 64 threads): the list's LDS and the wavefronts
@@ -42,7 +42,7 @@ from . import MechStepError, device_status, grid_info
 # (contact-list length, threads per block, run walk); the first is the
 # library default
 CHOICES = tuple((lst, nt, walk) for walk in ("lanes", "planes") for nt in (64, 256)
-                for lst in (32, 40))
+                for lst in (24, 40))
 
 
 def default_key(ws) -> str:

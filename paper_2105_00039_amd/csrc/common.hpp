@@ -22,7 +22,7 @@ constexpr int kSBMax = 12;
 constexpr int kBucketAgents = 3072;   // target mean agents per bucket
 constexpr int kSortThreads = 512;     // threads per block of the per-bucket sort
 constexpr int kSortStage = 4096;      // buckets up to this many agents are sorted in LDS
-constexpr int kMaxContacts = 32;      // per-lane contact list length of the gathers (default)
+constexpr int kMaxContacts = 24;      // per-lane contact list length of the gathers (default)
 constexpr int kLongList = 40;         // the longer list the forward gather may use
 constexpr int kForceBlockSmall = 64;  // the smaller block the forward gather may use
 constexpr int kBwdBlock = 64;         // threads per block of the backward gather

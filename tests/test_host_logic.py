@@ -58,9 +58,9 @@ def test_autotune_cache_loading(tmp_path):
     p.write_text(json.dumps({"f32|n2^21|occ2^1.5|sims1": 32}))
     table, path = autotune._load(str(p))
     assert table == {"f32|n2^21|occ2^1.5|sims1": 32}
-    # the library default comes first (kept on ties): 32-entry lists, 64
+    # the library default comes first (kept on ties): 24-entry lists, 64
     # threads, each lane walking its runs in turn; every triple appears once
-    assert autotune.CHOICES[0] == (32, 64, "lanes")
+    assert autotune.CHOICES[0] == (24, 64, "lanes")
     assert len(set(autotune.CHOICES)) == len(autotune.CHOICES) == 8
     assert {c[1] for c in autotune.CHOICES} == {64, 256}
     # entries of older caches (list length only, or list and block) read with
